@@ -1,0 +1,210 @@
+"""FP64 CPU oracle of the SSCN Gross-Pitaevskii step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline leg
+may import this package.  The product path (``paper_1709_04423_amd``) never
+imports it and shares no code with it.
+
+The numerics live in ``gp_oracle.c`` (plain C99, ``double complex``); this module
+only builds/loads that library and marshals numpy arrays.  Each function cites
+the part of the paper it follows: the program summary's "Solution method"
+(split-step Crank-Nicolson, imaginary- and real-time propagation) and "Nature of
+problem" (1d/2d/3d, fully anisotropic harmonic traps), plus the output
+quantities listed under "Summary of revisions" (energy, chemical potential,
+rms sizes).  Where the paper is silent the readings in ``gp_oracle.c``'s header
+apply.
+
+Arrays are numpy complex128, C-contiguous, shape ``(Nz, Ny, Nx)`` / ``(Ny, Nx)``
+/ ``(Nx,)`` -- x fastest.  ``n`` and ``dx`` are given x first.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+IMAG = 0
+REAL = 1
+OBS_FIELDS = ("norm", "mu", "energy", "ekin", "epot", "eint", "rms_x", "rms_y", "rms_z")
+
+
+def build(force: bool = False) -> str:
+    """Compile gp_oracle.c with gcc (FP64, no fast-math, OpenMP over lines)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+               "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        c_int, c_i64, c_d = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        lib.oracle_num_threads.restype = c_int
+        lib.oracle_thomas.argtypes = [c_i64, c_d, c_d, c_d, c_d, dp, dp]
+        lib.oracle_cn_axis.argtypes = [c_int, i64p, dp, c_d, c_int, c_int, c_int, dp]
+        lib.oracle_nonlinear.argtypes = [c_int, i64p, dp, c_d, c_int, dp, dp, c_i64, c_int,
+                                         c_i64, c_d, dp]
+        lib.oracle_step.argtypes = [c_int, i64p, dp, c_d, c_int, dp, dp, c_i64, c_int, c_d,
+                                    c_i64, c_i64, dp]
+        lib.oracle_observables.argtypes = [c_int, i64p, dp, dp, c_d, dp, dp]
+        lib.oracle_adjoint_step.argtypes = [c_int, i64p, dp, c_d, dp, dp, c_i64, c_int, c_d,
+                                            c_i64, dp, dp, dp, dp]
+        for f in (lib.oracle_thomas, lib.oracle_cn_axis, lib.oracle_nonlinear, lib.oracle_step,
+                  lib.oracle_observables, lib.oracle_adjoint_step):
+            f.restype = c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _grid_args(psi, dx):
+    n = np.array(psi.shape[::-1], dtype=np.int64)
+    dxa = np.array(np.broadcast_to(np.asarray(dx, dtype=np.float64), (len(n),)), dtype=np.float64)
+    return len(n), n, dxa
+
+
+def _omega_args(omega, ndim):
+    w = np.zeros(3, dtype=np.float64)
+    w[:ndim] = np.broadcast_to(np.asarray(omega, dtype=np.float64), (ndim,))
+    return w
+
+
+def _sched_args(sched):
+    if sched is None:
+        return None, 0
+    s = np.ascontiguousarray(sched, dtype=np.float64)
+    return s, len(s)
+
+
+def _check(status, what):
+    if status != 0:
+        raise RuntimeError(f"oracle {what} failed with status {status}")
+
+
+def _c128(psi):
+    a = np.ascontiguousarray(psi, dtype=np.complex128)
+    return a.copy() if a is psi else a
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def thomas(b: complex, e: complex, rhs: np.ndarray) -> np.ndarray:
+    """Plain Thomas solve of tridiag(e, b, e) x = rhs (constant coefficients)."""
+    lib = _load()
+    r = np.ascontiguousarray(rhs, dtype=np.complex128)
+    x = np.zeros_like(r)
+    _check(lib.oracle_thomas(len(r), b.real, b.imag, e.real, e.imag, _dp(r), _dp(x)), "thomas")
+    return x
+
+
+def cn_axis(psi, dx, dt, mode, axis, adjoint=False):
+    """One Crank-Nicolson kinetic substep along ``axis`` (0 = x); returns a new array."""
+    lib = _load()
+    out = _c128(psi)
+    ndim, n, dxa = _grid_args(out, dx)
+    _check(lib.oracle_cn_axis(ndim, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dxa),
+                              dt, mode, axis, int(adjoint), _dp(out)), "cn_axis")
+    return out
+
+
+def nonlinear(psi, dx, dt, mode, omega, g, sched=None, sched_axis=0, step=0):
+    """Pointwise potential + nonlinear propagator of step ``step``; returns a new array."""
+    lib = _load()
+    out = _c128(psi)
+    ndim, n, dxa = _grid_args(out, dx)
+    w = _omega_args(omega, ndim)
+    s, slen = _sched_args(sched)
+    _check(lib.oracle_nonlinear(ndim, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dxa),
+                                dt, mode, _dp(w), _dp(s) if s is not None else None, slen,
+                                sched_axis, step, g, _dp(out)), "nonlinear")
+    return out
+
+
+def step(psi, dx, dt, mode, omega, g, nsteps=1, sched=None, sched_axis=0, n0=0):
+    """``nsteps`` full SSCN steps (N substep, CN per axis x..z, imag renormalisation)."""
+    lib = _load()
+    out = _c128(psi)
+    ndim, n, dxa = _grid_args(out, dx)
+    w = _omega_args(omega, ndim)
+    s, slen = _sched_args(sched)
+    _check(lib.oracle_step(ndim, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dxa), dt,
+                           mode, _dp(w), _dp(s) if s is not None else None, slen, sched_axis, g,
+                           n0, nsteps, _dp(out)), "step")
+    return out
+
+
+def observables(psi, dx, omega, g) -> dict:
+    """norm, mu, energy, ekin, epot, eint and uncentred rms sizes of ``psi``."""
+    lib = _load()
+    a = np.ascontiguousarray(psi, dtype=np.complex128)
+    ndim, n, dxa = _grid_args(a, dx)
+    w = _omega_args(omega, ndim)
+    out = np.zeros(9, dtype=np.float64)
+    _check(lib.oracle_observables(ndim, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  _dp(dxa), _dp(w), g, _dp(a), _dp(out)), "observables")
+    return dict(zip(OBS_FIELDS, out.tolist()))
+
+
+def adjoint_step(psi_in, lam, dx, dt, omega, g, sched=None, sched_axis=0, step=0):
+    """Adjoint of one real-time step.  Returns (lambda_in, dL/dw_s(step) / w_s(step), dL/dg part).
+
+    ``psi_in`` is the step's input state, ``lam`` the gradient (dL/dRe + i dL/dIm)
+    of its output."""
+    lib = _load()
+    p = np.ascontiguousarray(psi_in, dtype=np.complex128)
+    out = _c128(lam)
+    ndim, n, dxa = _grid_args(p, dx)
+    w = _omega_args(omega, ndim)
+    s, slen = _sched_args(sched)
+    dth = np.zeros(1)
+    dg = np.zeros(1)
+    _check(lib.oracle_adjoint_step(ndim, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   _dp(dxa), dt, _dp(w), _dp(s) if s is not None else None, slen,
+                                   sched_axis, g, step, _dp(p), _dp(out), _dp(dth), _dp(dg)),
+           "adjoint_step")
+    return out, float(dth[0]), float(dg[0])
+
+
+def overlap_loss(psi_T, psi_target, dx):
+    """Loss 1 - |c|^2, c = dV sum conj(target) psi_T, and its gradient -2 c dV target."""
+    dv = float(np.prod(np.broadcast_to(np.asarray(dx, dtype=np.float64), (psi_T.ndim,))))
+    c = dv * np.vdot(psi_target.ravel(), psi_T.ravel())
+    return 1.0 - abs(c) ** 2, -2.0 * c * dv * psi_target
+
+
+def gradient(psi0, psi_target, dx, dt, omega, g, sched, sched_axis=0):
+    """Loss and its gradients w.r.t. the schedule and g, for a real-time run of
+    len(sched) steps from psi0 (plain full-storage reverse sweep)."""
+    T = len(sched)
+    states = [np.ascontiguousarray(psi0, dtype=np.complex128)]
+    for k in range(T):
+        states.append(step(states[-1], dx, dt, REAL, omega, g, 1, sched, sched_axis, k))
+    loss, lam = overlap_loss(states[-1], psi_target, dx)
+    dsched = np.zeros(T)
+    dg = 0.0
+    for k in range(T - 1, -1, -1):
+        lam, dth, dgk = adjoint_step(states[k], lam, dx, dt, omega, g, sched, sched_axis, k)
+        dsched[k] = dth * sched[k]
+        dg += dgk
+    return loss, dsched, dg, lam

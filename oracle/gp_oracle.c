@@ -1,0 +1,389 @@
+/*
+ * gp_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow FP64 CPU reference of the split-step Crank-Nicolson (SSCN)
+ * time step for the dimensionless Gross-Pitaevskii equation
+ *
+ *     i dpsi/dt = [ -1/2 laplacian + V + g |psi|^2 ] psi,   V = 1/2 sum_a w_a^2 x_a^2,
+ *
+ * in 1, 2 or 3 dimensions, in imaginary time (stationary states) and real time
+ * (dynamics).  The paper (program summary, "Solution method" and "Nature of
+ * problem") names the method -- split-step Crank-Nicolson discretisation in
+ * space and time, propagated in imaginary or real time -- and defers the
+ * formulas to its earlier publications; the readings used where it is silent
+ * are listed below and in the design notes.
+ *
+ * Only tests/, the package smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header, table or helper with the GPU
+ * path; nothing here is tuned.  OpenMP splits independent grid lines over host
+ * cores (as the paper's OpenMP programs do) only to time a CPU baseline; every
+ * floating-point reduction is a serial loop in a fixed order, so results do not
+ * depend on the thread count.
+ *
+ * Readings of the paper (it states none of these):
+ *  - grid: x_{a,i} = -N_a dx_a / 2 + i dx_a, i = 0..N_a-1; dV = prod dx_a;
+ *  - Laplacian: 3-point second difference per axis, zero values at the ghost
+ *    points i = -1 and i = N_a (zero Dirichlet walls);
+ *  - one step (Lie splitting): pointwise potential + nonlinear propagator with
+ *    |psi|^2 taken before the substep, then one Crank-Nicolson kinetic substep
+ *    per axis in the order x, y, z; imaginary time then renormalises to 1;
+ *  - CN substep along axis a with r = dt / (4 dx_a^2):
+ *        real time : b = 1 + 2 i r, e = -i r;     imaginary time: b = 1 + 2 r, e = -r
+ *        solve  b u'_i + e (u'_{i-1} + u'_{i+1}) = (2 - b) u_i - e (u_{i-1} + u_{i+1})
+ *    with the plain Thomas algorithm (no pivoting; |b| > 2|e| always holds);
+ *  - observables: rectangle sums; kinetic energy from forward differences over
+ *    i = -1..N_a-1 with zero ghosts (equal to <psi, T psi> for the same T);
+ *    mu = Ekin + Epot + 2 Eint, E = Ekin + Epot + Eint, uncentred rms sizes;
+ *  - trap schedule: step n may replace w on one axis by sched[n] (0 <= n < len).
+ *
+ * Array layout: complex128 values stored as interleaved (re, im) doubles, x the
+ * fastest index: p = i + N0 (j + N1 k).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORACLE_IMAG 0
+#define ORACLE_REAL 1
+
+/* ------------------------------------------------------------------ grid */
+
+static double coord(int64_t i, int64_t n, double dx)
+{
+    return (double)i * dx - 0.5 * (double)n * dx;
+}
+
+static int64_t total_points(int ndim, const int64_t *n)
+{
+    int64_t t = 1;
+    for (int a = 0; a < ndim; ++a) t *= n[a];
+    return t;
+}
+
+static int64_t axis_stride(int ndim, const int64_t *n, int axis)
+{
+    int64_t s = 1;
+    for (int a = 0; a < axis && a < ndim; ++a) s *= n[a];
+    return s;
+}
+
+/* Trap frequency of axis a during step `step` (schedule overrides one axis). */
+static double omega_at(const double *omega, const double *sched, int64_t sched_len,
+                       int sched_axis, int64_t step, int a)
+{
+    if (sched && a == sched_axis && step >= 0 && step < sched_len) return sched[step];
+    return omega[a];
+}
+
+static void point_coords(int ndim, const int64_t *n, const double *dx, int64_t p, double *x)
+{
+    int64_t rem = p;
+    for (int a = 0; a < ndim; ++a) {
+        int64_t i = rem % n[a];
+        rem /= n[a];
+        x[a] = coord(i, n[a], dx[a]);
+    }
+}
+
+static double potential(int ndim, const double *x, const double *w)
+{
+    double v = 0.0;
+    for (int a = 0; a < ndim; ++a) v += 0.5 * w[a] * w[a] * x[a] * x[a];
+    return v;
+}
+
+static double abs2(cplx z) { return creal(z) * creal(z) + cimag(z) * cimag(z); }
+
+/* --------------------------------------------------- Crank-Nicolson parts */
+
+/* Coefficients of the implicit side of the CN substep along one axis.
+ * `adjoint` conjugates them: the Hermitian adjoint of the real-time CN map is
+ * the same map with dt -> -dt. */
+static void cn_coefficients(double dt, double dxa, int mode, int adjoint, cplx *b, cplx *e)
+{
+    double r = dt / (4.0 * dxa * dxa);
+    if (mode == ORACLE_REAL) {
+        *b = 1.0 + 2.0 * I * r;
+        *e = -I * r;
+    } else {
+        *b = 1.0 + 2.0 * r;
+        *e = -r;
+    }
+    if (adjoint) {
+        *b = conj(*b);
+        *e = conj(*e);
+    }
+}
+
+/* Plain Thomas algorithm for tridiag(e, b, e) x = rhs of size n.
+ * work holds n values.  Returns 0, or -1 if the matrix is not strictly
+ * diagonally dominant (then the elimination is not known to be stable). */
+static int thomas(int64_t n, cplx b, cplx e, const cplx *rhs, cplx *x, cplx *work)
+{
+    if (n <= 0) return 0;
+    if (!(cabs(b) > 2.0 * cabs(e))) return -1;
+    work[0] = e / b;
+    x[0] = rhs[0] / b;
+    for (int64_t i = 1; i < n; ++i) {
+        cplx denom = b - e * work[i - 1];
+        work[i] = e / denom;
+        x[i] = (rhs[i] - e * x[i - 1]) / denom;
+    }
+    for (int64_t i = n - 2; i >= 0; --i) x[i] -= work[i] * x[i + 1];
+    return 0;
+}
+
+/* One CN kinetic substep along `axis`, in place, over every line of the grid. */
+static int cn_axis(int ndim, const int64_t *n, const double *dx, double dt, int mode,
+                   int axis, int adjoint, cplx *psi)
+{
+    cplx b, e;
+    cn_coefficients(dt, dx[axis], mode, adjoint, &b, &e);
+    if (!(cabs(b) > 2.0 * cabs(e))) return -1;
+    const int64_t len = n[axis];
+    const int64_t stride = axis_stride(ndim, n, axis);
+    const int64_t nlines = total_points(ndim, n) / len;
+    int status = 0;
+
+#pragma omp parallel
+    {
+        cplx *u = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+        cplx *rhs = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+        cplx *out = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+        cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)len);
+#pragma omp for schedule(static)
+        for (int64_t line = 0; line < nlines; ++line) {
+            /* first point of the line: split the line index into the part
+             * below the axis (inner) and above it (outer). */
+            int64_t inner = line % stride;
+            int64_t outer = line / stride;
+            int64_t base = inner + outer * stride * len;
+            for (int64_t i = 0; i < len; ++i) u[i] = psi[base + i * stride];
+            for (int64_t i = 0; i < len; ++i) {
+                cplx left = (i > 0) ? u[i - 1] : 0.0;
+                cplx right = (i + 1 < len) ? u[i + 1] : 0.0;
+                rhs[i] = (2.0 - b) * u[i] - e * (left + right);
+            }
+            if (thomas(len, b, e, rhs, out, work) != 0) {
+#pragma omp atomic write
+                status = -1;
+            }
+            for (int64_t i = 0; i < len; ++i) psi[base + i * stride] = out[i];
+        }
+        free(u);
+        free(rhs);
+        free(out);
+        free(work);
+    }
+    return status;
+}
+
+/* Pointwise potential + nonlinear propagator for step `step`. */
+static void nonlinear(int ndim, const int64_t *n, const double *dx, double dt, int mode,
+                      const double *omega, const double *sched, int64_t sched_len,
+                      int sched_axis, int64_t step, double g, cplx *psi)
+{
+    double w[3];
+    for (int a = 0; a < ndim; ++a) w[a] = omega_at(omega, sched, sched_len, sched_axis, step, a);
+    const int64_t total = total_points(ndim, n);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < total; ++p) {
+        double x[3];
+        point_coords(ndim, n, dx, p, x);
+        double theta = dt * (potential(ndim, x, w) + g * abs2(psi[p]));
+        if (mode == ORACLE_REAL)
+            psi[p] *= cexp(-I * theta);
+        else
+            psi[p] *= exp(-theta);
+    }
+}
+
+static double norm_of(int ndim, const int64_t *n, const double *dx, const cplx *psi)
+{
+    double dv = 1.0;
+    for (int a = 0; a < ndim; ++a) dv *= dx[a];
+    double s = 0.0;
+    const int64_t total = total_points(ndim, n);
+    for (int64_t p = 0; p < total; ++p) s += abs2(psi[p]);
+    return s * dv;
+}
+
+static int check_args(int ndim, const int64_t *n, const double *dx, double dt, int mode)
+{
+    if (ndim < 1 || ndim > 3 || !n || !dx) return -2;
+    for (int a = 0; a < ndim; ++a)
+        if (n[a] < 1 || !(dx[a] > 0.0)) return -2;
+    if (!(dt > 0.0) || (mode != ORACLE_IMAG && mode != ORACLE_REAL)) return -2;
+    return 0;
+}
+
+/* ------------------------------------------------------------ public API */
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Thomas solve of tridiag(e, b, e) x = rhs; arrays interleaved (re, im). */
+int oracle_thomas(int64_t n, double br, double bi, double er, double ei, const double *rhs,
+                  double *x)
+{
+    if (n < 0) return -2;
+    cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(n > 0 ? n : 1));
+    int s = thomas(n, br + I * bi, er + I * ei, (const cplx *)rhs, (cplx *)x, work);
+    free(work);
+    return s;
+}
+
+/* One CN kinetic substep along one axis (adjoint != 0: the conjugate map). */
+int oracle_cn_axis(int ndim, const int64_t *n, const double *dx, double dt, int mode, int axis,
+                   int adjoint, double *psi)
+{
+    int s = check_args(ndim, n, dx, dt, mode);
+    if (s) return s;
+    if (axis < 0 || axis >= ndim) return -2;
+    return cn_axis(ndim, n, dx, dt, mode, axis, adjoint, (cplx *)psi);
+}
+
+/* Pointwise potential + nonlinear substep alone (step index selects the schedule). */
+int oracle_nonlinear(int ndim, const int64_t *n, const double *dx, double dt, int mode,
+                     const double *omega, const double *sched, int64_t sched_len,
+                     int sched_axis, int64_t step, double g, double *psi)
+{
+    int s = check_args(ndim, n, dx, dt, mode);
+    if (s) return s;
+    nonlinear(ndim, n, dx, dt, mode, omega, sched, sched_len, sched_axis, step, g, (cplx *)psi);
+    return 0;
+}
+
+/* `nsteps` full SSCN steps, the first with schedule index n0. */
+int oracle_step(int ndim, const int64_t *n, const double *dx, double dt, int mode,
+                const double *omega, const double *sched, int64_t sched_len, int sched_axis,
+                double g, int64_t n0, int64_t nsteps, double *psi_ri)
+{
+    int s = check_args(ndim, n, dx, dt, mode);
+    if (s) return s;
+    cplx *psi = (cplx *)psi_ri;
+    const int64_t total = total_points(ndim, n);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        nonlinear(ndim, n, dx, dt, mode, omega, sched, sched_len, sched_axis, n0 + k, g, psi);
+        for (int a = 0; a < ndim; ++a)
+            if (cn_axis(ndim, n, dx, dt, mode, a, 0, psi) != 0) return -1;
+        if (mode == ORACLE_IMAG) {
+            double nrm = norm_of(ndim, n, dx, psi);
+            if (!(nrm > 0.0) || !isfinite(nrm)) return -3;
+            double scale = 1.0 / sqrt(nrm);
+            for (int64_t p = 0; p < total; ++p) psi[p] *= scale;
+        }
+    }
+    return 0;
+}
+
+/* Observables of psi with static trap omega:
+ * out = {norm, mu, energy, ekin, epot, eint, rms_x, rms_y, rms_z}. */
+int oracle_observables(int ndim, const int64_t *n, const double *dx, const double *omega,
+                       double g, const double *psi_ri, double *out)
+{
+    if (ndim < 1 || ndim > 3) return -2;
+    const cplx *psi = (const cplx *)psi_ri;
+    const int64_t total = total_points(ndim, n);
+    double dv = 1.0;
+    for (int a = 0; a < ndim; ++a) dv *= dx[a];
+
+    double sum_n = 0.0, sum_v = 0.0, sum_4 = 0.0, sum_x2[3] = {0.0, 0.0, 0.0};
+    for (int64_t p = 0; p < total; ++p) {
+        double x[3];
+        point_coords(ndim, n, dx, p, x);
+        double d = abs2(psi[p]);
+        sum_n += d;
+        sum_v += potential(ndim, x, omega) * d;
+        sum_4 += d * d;
+        for (int a = 0; a < ndim; ++a) sum_x2[a] += x[a] * x[a] * d;
+    }
+
+    /* kinetic: forward differences along each axis, ghosts zero on both ends */
+    double ekin = 0.0;
+    for (int a = 0; a < ndim; ++a) {
+        const int64_t len = n[a];
+        const int64_t stride = axis_stride(ndim, n, a);
+        const int64_t nlines = total / len;
+        double s = 0.0;
+        for (int64_t line = 0; line < nlines; ++line) {
+            int64_t base = (line % stride) + (line / stride) * stride * len;
+            for (int64_t i = -1; i < len; ++i) {
+                cplx lo = (i >= 0) ? psi[base + i * stride] : 0.0;
+                cplx hi = (i + 1 < len) ? psi[base + (i + 1) * stride] : 0.0;
+                s += abs2(hi - lo);
+            }
+        }
+        ekin += 0.5 * dv * s / (dx[a] * dx[a]);
+    }
+
+    double norm = dv * sum_n;
+    double epot = dv * sum_v;
+    double eint = 0.5 * g * dv * sum_4;
+    out[0] = norm;
+    out[1] = ekin + epot + 2.0 * eint;
+    out[2] = ekin + epot + eint;
+    out[3] = ekin;
+    out[4] = epot;
+    out[5] = eint;
+    for (int a = 0; a < 3; ++a) out[6 + a] = (a < ndim) ? sqrt(dv * sum_x2[a] / norm) : 0.0;
+    return 0;
+}
+
+/* Adjoint of one real-time step n (schedule index `step`), in the gradient
+ * convention G = dL/dRe + i dL/dIm.
+ *
+ * Forward step: u = psi e^{-i theta}, theta = dt (V_n + g |psi|^2); then the CN
+ * maps X, Y, Z.  Given lambda = G of the step output and psi = the step input,
+ * on return lambda = G of the step input and
+ *   *dtheta_w = dt * sum_p w_p x_{s,p}^2   (times w_s(n) gives dL/dw_s(n)),
+ *   *dg       = dt * sum_p w_p |u_p|^2,
+ * with w = Im(conj(lambda_u) u) and lambda_u the gradient of u. */
+int oracle_adjoint_step(int ndim, const int64_t *n, const double *dx, double dt,
+                        const double *omega, const double *sched, int64_t sched_len,
+                        int sched_axis, double g, int64_t step, const double *psi_ri,
+                        double *lambda_ri, double *dtheta_w, double *dg)
+{
+    int s = check_args(ndim, n, dx, dt, ORACLE_REAL);
+    if (s) return s;
+    cplx *lam = (cplx *)lambda_ri;
+    const cplx *psi = (const cplx *)psi_ri;
+
+    /* the CN maps in reverse order, each replaced by its adjoint */
+    for (int a = ndim - 1; a >= 0; --a)
+        if (cn_axis(ndim, n, dx, dt, ORACLE_REAL, a, 1, lam) != 0) return -1;
+
+    double w_axis[3];
+    for (int a = 0; a < ndim; ++a)
+        w_axis[a] = omega_at(omega, sched, sched_len, sched_axis, step, a);
+    const int64_t total = total_points(ndim, n);
+    double sum_wx = 0.0, sum_wd = 0.0;
+    for (int64_t p = 0; p < total; ++p) {
+        double x[3];
+        point_coords(ndim, n, dx, p, x);
+        double d = abs2(psi[p]);
+        double theta = dt * (potential(ndim, x, w_axis) + g * d);
+        cplx u = psi[p] * cexp(-I * theta);
+        double w = cimag(conj(lam[p]) * u);
+        lam[p] = cexp(I * theta) * lam[p] + 2.0 * dt * g * w * psi[p];
+        int sa = (sched_axis >= 0 && sched_axis < ndim) ? sched_axis : 0;
+        sum_wx += w * x[sa] * x[sa];
+        sum_wd += w * d;
+    }
+    *dtheta_w = dt * sum_wx;
+    *dg = dt * sum_wd;
+    return 0;
+}
