@@ -1,0 +1,206 @@
+/*
+ * gp.h -- C ABI of libgp: split-step Crank-Nicolson (SSCN) time steps of the
+ * dimensionless Gross-Pitaevskii equation on one AMD Instinct MI355X (gfx950).
+ *
+ *     i dpsi/dt = [ -1/2 laplacian + V + g |psi|^2 ] psi,   V = 1/2 sum_a w_a^2 x_a^2
+ *
+ * The paper's program summary ("Nature of problem", "Solution method") defines
+ * the problem -- 1d/2d/3d condensates in fully anisotropic harmonic traps --
+ * and the method: split-step Crank-Nicolson discretisation in space and time,
+ * propagated in imaginary time (stationary states) or real time (dynamics);
+ * "Summary of revisions" lists the outputs (energy, chemical potential, rms
+ * sizes).  One step, as computed here:
+ *   1. pointwise potential + nonlinear propagator, |psi|^2 taken before it:
+ *        real time  psi <- psi exp(-i theta),  imaginary time psi <- psi exp(-theta),
+ *        theta = dt (V + g |psi|^2);
+ *   2. one Crank-Nicolson kinetic substep per axis, x then y then z, each a
+ *      constant-coefficient tridiagonal solve along every grid line
+ *      (3-point Laplacian, zero values at the ghost points i = -1 and i = N_a);
+ *   3. imaginary time only: renormalise to dV sum |psi|^2 = 1.
+ * Grid: x_{a,i} = (i - N_a/2) dx_a, i = 0..N_a-1;  dV = prod dx_a.
+ *
+ * Conventions shared by every entry point
+ *  - Wavefunctions are caller-owned DEVICE buffers of interleaved (re, im)
+ *    values, complex128 (GP_C128) or complex64 (GP_C64), dense, x fastest:
+ *    element (i, j, k) at i + N0 (j + N1 k).  A torch tensor of shape
+ *    (Nz, Ny, Nx) and dtype complex128/complex64 has exactly this layout.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; only gp_observables, gp_plan_timing_read and the
+ *    batch autotuner synchronise it.
+ *  - Every function returns gp_status and never throws or aborts.  Arguments
+ *    are checked before any HIP call.  An asynchronous device fault surfaces as
+ *    GP_EHIP on a later call.  gp_last_error() gives a message for the last
+ *    failure on the calling thread.
+ *  - A plan is not thread-safe; separate plans may run on separate streams.
+ *    A plan binds to the device that is current when it is created.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GP_OK = 0,
+    GP_EINVAL = -1,        /* bad argument (null pointer, size, dt, dx, enum) */
+    GP_ENOMEM = -2,        /* device or host allocation failed */
+    GP_EHIP = -3,          /* HIP runtime error (message in gp_last_error) */
+    GP_ENONFINITE = -4,    /* non-finite norm or energy found */
+    GP_EUNSUPPORTED = -5,  /* valid request this build does not implement */
+    GP_ETIMEOUT = -6       /* a bounded device-side wait gave up */
+} gp_status;
+
+typedef enum { GP_IMAG = 0, GP_REAL = 1 } gp_mode;
+
+/* GP_C64: complex64 storage and FP32 arithmetic for the bulk of the step, with
+ * FP64 norm/energy reductions and an FP64 renormalisation factor. */
+typedef enum { GP_C128 = 0, GP_C64 = 1 } gp_prec;
+
+/* Harmonic trap V = 1/2 sum_a omega[a]^2 x_a^2.  Optionally a host array of
+ * per-step frequencies replaces omega[sched_axis] in the potential substep of
+ * step n for 0 <= n < sched_len (the plan copies it).  Observables always use
+ * the static omega[]. */
+typedef struct {
+    double omega[3];
+    const double *omega_sched;
+    int64_t sched_len;
+    int sched_axis;
+} gp_trap;
+
+/* Observables (rectangle sums over the grid, FP64 accumulation):
+ *   norm  = dV sum |psi|^2
+ *   ekin  = dV/2 sum_a sum_lines sum_{i=-1}^{N_a-1} |u_{i+1}-u_i|^2 / dx_a^2  (zero ghosts)
+ *   epot  = dV sum V |psi|^2,   eint = g dV/2 sum |psi|^4
+ *   energy = ekin + epot + eint,  mu = ekin + epot + 2 eint
+ *   rms[a] = sqrt(dV sum x_a^2 |psi|^2 / norm)   (0 for absent axes)          */
+typedef struct {
+    double norm, mu, energy, ekin, epot, eint, rms[3];
+} gp_obs;
+
+/* Read-only description of a plan (host data). */
+typedef struct {
+    int ndim;
+    int64_t n[3];
+    int window[3];        /* back-substitution window K per axis; -1 = exact two-pass solve */
+    double rho[3];        /* max |c'_i| of the Thomas recurrence per axis */
+    double window_bound[3]; /* rho^(K+1): bound on the window's relative truncation */
+    int64_t step;         /* index of the next step (selects the trap schedule) */
+    int64_t device_bytes; /* device memory owned by the plan */
+} gp_plan_info;
+
+typedef struct gp_plan gp_plan;
+typedef struct gp_batch gp_batch;
+
+/* ------------------------------------------------------------ core path */
+
+/* Create a plan for an ndim-dimensional grid n[0..ndim) (x first) with
+ * spacings dx[0..ndim), time step dt > 0, mode, trap (may be NULL: all
+ * omega = 0), nonlinearity g and precision.  Precomputes the per-axis Thomas
+ * coefficients in FP64 on the host (rounded once to FP32 for GP_C64) and
+ * allocates the plan's device buffers on the current device.
+ * Errors: GP_EINVAL (ndim not 1..3, n < 1, dx <= 0, dt <= 0 or non-finite, bad
+ * enum, bad schedule), GP_ENOMEM, GP_EHIP (no usable device). */
+gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt,
+                         gp_mode mode, const gp_trap *trap, double g, gp_prec prec);
+
+/* Free the plan and its device buffers (NULL is allowed). */
+gp_status gp_plan_destroy(gp_plan *plan);
+
+/* Advance psi (device, in place, layout above) by nsteps >= 0 SSCN steps on
+ * `stream`; asynchronous.  In imaginary time psi is returned with unit norm.
+ * The plan's step index advances by nsteps. */
+gp_status gp_step(gp_plan *plan, void *psi, int64_t nsteps, void *stream);
+
+/* Observables of psi (device) into *out (host); synchronises `stream`.
+ * Returns GP_ENONFINITE (with *out filled) if norm or energy is not finite. */
+gp_status gp_observables(gp_plan *plan, const void *psi, gp_obs *out, void *stream);
+
+/* Set / get the index of the next step (resume, recompute segments). */
+gp_status gp_plan_set_step(gp_plan *plan, int64_t step);
+gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info);
+
+/* Host-only (no GPU needed): one axis's Thomas table exactly as a plan stores
+ * it, for checking.  The CN substep along an axis of n points is solved in the
+ * form scaled by 1/e (unit off-diagonals):
+ *     tridiag(1, delta_p, 1) u' = beta_p u_p - (u_{p-1} + u_{p+1}),
+ * factorised as y_p = (rhs_p - y_{p-1}) c'_p, u'_p = y_p - c'_p u'_{p+1}, where
+ * c'_0 = e/b, c'_p = e/(b - e c'_{p-1}) are rounded to the precision and
+ * delta_p = 1/c'_p + c'_{p-1} is what the rounded values multiply out to;
+ * beta_p = -conj(delta_p) in real time, -2/r - delta_p in imaginary time
+ * (r = dt/(4 dx^2)).  Outputs, for p = 0..n-1: c[2p], c[2p+1] = c'_p and
+ * beta[2p], beta[2p+1] = beta_p (interleaved complex, conjugated if adjoint),
+ * *window = back-substitution window K (-1: exact two-pass solver), *rho =
+ * max |c'_p|. */
+gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec prec, int adjoint,
+                          double *c, double *beta, int *window, double *rho);
+
+const char *gp_strerror(gp_status s);
+const char *gp_last_error(void);
+
+/* ------------------------------------------------------ adjoint form */
+
+/* Reverse of `nsteps` real-time steps n_first .. n_first+nsteps-1, in the
+ * gradient convention G = dL/dRe + i dL/dIm (PyTorch's for a real loss).
+ *   states : device, nsteps consecutive wavefunctions; states[k] is the INPUT
+ *            of step n_first + k (same precision/layout as psi)
+ *   lambda : device, in place: on entry G of the output of the last step, on
+ *            return G of the input of step n_first
+ *   dsched : device FP64[nsteps] or NULL: dsched[k] = dL/d omega_s(n_first+k)
+ *            for the schedule axis s (written, not accumulated)
+ *   dg     : device FP64[1] or NULL: dL/dg accumulated (+=) over the steps
+ * Per step n, with u the output of the potential substep and lambda_u its
+ * gradient (obtained by the conjugate Crank-Nicolson solves z, y, x):
+ *   w = Im(conj(lambda_u) u),  lambda_psi = e^{i theta} lambda_u + 2 dt g w psi,
+ *   dL/d omega_s(n) = dt omega_s(n) sum w x_s^2,   dL/dg += dt sum w |u|^2.
+ * Real-time plans only (GP_EUNSUPPORTED otherwise).  Asynchronous. */
+gp_status gp_step_adjoint(gp_plan *plan, const void *states, void *lambda, int64_t n_first,
+                          int64_t nsteps, double *dsched, double *dg, void *stream);
+
+/* ------------------------------------------------------ batched form */
+
+/* A batch of `count` independent 2D problems (grids n[k][0..1], spacings
+ * dx[k] (same on both axes), steps dt[k], traps omega[k][0..1], g[k]), all in
+ * one mode and precision, advanced together by gp_batch_step in one
+ * persistent launch.  Plans are built per problem as in gp_plan_create. */
+gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n /* [count][2] */,
+                          const double *dx, const double *dt, gp_mode mode,
+                          const double *omega /* [count][2] */, const double *g, gp_prec prec);
+gp_status gp_batch_destroy(gp_batch *batch);
+
+/* Advance every problem k (psis[k]: device pointer of problem k's grid) by
+ * nsteps steps.  The pointer array is host memory.  Asynchronous. */
+gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream);
+
+/* Time the candidate tile shapes of the batch kernel on scratch copies of the
+ * problems and keep the fastest; cache_path (may be NULL) is a text file of
+ * previous results keyed by problem size, read first and updated.  Synchronises. */
+gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *stream);
+
+/* Observables of problem k of a batch (as gp_observables). */
+gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream);
+
+/* ---------------------------------------------------- measurement aids */
+
+/* Per-kernel timing with HIP events recorded on the plan's launch stream around
+ * every kernel launch; capacity = number of launches to record (0 disables). */
+gp_status gp_plan_timing_enable(gp_plan *plan, int64_t capacity);
+
+/* Synchronise the events and report, per kernel kind (names in
+ * gp_kernel_name(kind), kind = 0..GP_NUM_KERNEL_KINDS-1), the number of
+ * recorded launches and their total duration in milliseconds; clears the log. */
+#define GP_NUM_KERNEL_KINDS 12
+gp_status gp_plan_timing_read(gp_plan *plan, int64_t *counts, double *total_ms);
+const char *gp_kernel_name(int kind);
+
+/* Plain device copy of `bytes` (multiple of 16) from src to dst: the
+ * reference kernel for bandwidth and counter calibration.  Asynchronous. */
+gp_status gp_copy_probe(void *dst, const void *src, int64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

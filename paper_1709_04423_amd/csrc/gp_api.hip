@@ -1,0 +1,525 @@
+// Host runtime of libgp: argument checking, plan construction (FP64 Thomas
+// tables on the host, device buffers), the per-step launch sequence, the
+// adjoint driver, observables and the measurement aids.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+gp_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return GP_EHIP;
+}
+
+size_t elem_bytes(gp_prec prec) { return prec == GP_C128 ? 16 : 8; }
+
+double coord0(int64_t n) { return -0.5 * (double)n; }
+
+void timing_begin(gp_plan *p, int kind, hipStream_t s)
+{
+    Timing &T = p->timing;
+    if (T.capacity == 0 || T.used >= T.capacity) return;
+    T.kind[T.used] = kind;
+    hipEventRecord(T.ev[2 * T.used], s);
+}
+
+void timing_end(gp_plan *p, hipStream_t s)
+{
+    Timing &T = p->timing;
+    if (T.capacity == 0 || T.used >= T.capacity) return;
+    hipEventRecord(T.ev[2 * T.used + 1], s);
+    ++T.used;
+}
+
+// c'_p of the scaled CN system tridiag(1, b/e, 1) for p = 0..n-1 (equal to
+// e m_p of the Thomas algorithm on tridiag(e, b, e)), in extended precision:
+//   c'_0 = 1/(b/e),  c'_p = 1/(b/e - c'_{p-1});
+//   real time b/e = -2 + i/r, imaginary time b/e = -2 - 1/r,  r = dt/(4 dx^2).
+// rho = max |c'_p| over p < n-1: the contraction factor of the back substitution.
+static void thomas_c(int64_t n, double r, gp_mode mode, std::vector<std::complex<long double>> &c,
+                     double &rho)
+{
+    using cl = std::complex<long double>;
+    const long double kappa = 1.0L / (long double)r;
+    const cl be = mode == GP_REAL ? cl(-2.0L, kappa) : cl(-2.0L - kappa, 0.0L);
+    c.assign(n, cl(0.0L, 0.0L));
+    cl prev(0.0L, 0.0L);
+    rho = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        c[p] = 1.0L / (be - prev);
+        prev = c[p];
+        if (p + 1 < n) rho = std::fmax(rho, (double)std::abs(c[p]));
+    }
+}
+
+// Device rows (p = -1 .. rows-2) of precision T: c'_p rounded to T, and the
+// explicit-side diagonal beta_p derived from the rounded c' values:
+//   delta_p = 1/c'_p + c'_{p-1} (the diagonal the stored factors multiply out to),
+//   real time beta_p = -conj(delta_p), imaginary time beta_p = -2/r - delta_p,
+// with Im beta_p split into T hi + T lo.  conj conjugates every entry (the
+// adjoint map).  Rows outside the line are zero.
+template <typename T>
+static void table_rows(const std::vector<std::complex<long double>> &c, int64_t rows, double r, gp_mode mode,
+                       bool conj, std::vector<T> &out)
+{
+    using cl = std::complex<long double>;
+    const int64_t n = (int64_t)c.size();
+    out.assign(6 * rows, T(0));
+    cl prev(0.0L, 0.0L);
+    const long double sg = conj ? -1.0L : 1.0L;
+    for (int64_t p = 0; p < n; ++p) {
+        const T cr = (T)c[p].real(), ci = (T)c[p].imag();
+        const cl cs((long double)cr, (long double)ci);
+        const cl delta = 1.0L / cs + prev;
+        prev = cs;
+        cl beta = mode == GP_REAL ? -std::conj(delta) : cl(-2.0L / (long double)r, 0.0L) - delta;
+        const T br = (T)beta.real();
+        const T bi_hi = (T)beta.imag();
+        const T bi_lo = (T)(beta.imag() - (long double)bi_hi);
+        T *row = &out[6 * (p + 1)];
+        row[0] = cr;
+        row[1] = (T)(sg * ci);
+        row[2] = br;
+        row[3] = (T)(sg * bi_hi);
+        row[4] = (T)(sg * bi_lo);
+        row[5] = T(0);
+    }
+}
+
+// Window K (smallest K with rho^(K+1) <= tol), ring geometry, or -1 for the
+// exact two-pass solver when the ring does not fit in LDS.
+static void choose_window(AxisPlan &A, gp_prec prec)
+{
+    const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -30);
+    int K = 0;
+    double bound = A.rho;
+    while (bound > tol && K < 100000) {
+        bound *= A.rho;
+        ++K;
+    }
+    if (A.rho == 0.0) bound = 0.0;
+    const int D = (K + 1 + kBlock - 1) / kBlock;
+    int L = 1;
+    while (L < (D + 1) * kBlock) L <<= 1;
+    const int64_t lds = (int64_t)L * kLanes * (int64_t)elem_bytes(prec);
+    const int64_t nblocks = (A.n + kBlock - 1) / kBlock;
+    if (lds <= kMaxLdsBytes) {
+        A.K = K;
+        A.D = D;
+        A.L = L;
+        A.bound = bound;
+        A.npad = (nblocks + D) * kBlock;
+    } else {
+        A.K = -1;
+        A.D = 0;
+        A.L = 0;
+        A.bound = 0.0;
+        A.npad = A.n + 1;
+    }
+    if (A.npad < A.n + 1) A.npad = A.n + 1;
+}
+
+static gp_status alloc(void **ptr, size_t bytes, int64_t &counter)
+{
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EHIP;
+    }
+    counter += (int64_t)bytes;
+    return GP_OK;
+}
+
+// Upload one axis's table (forward or conjugate) to the device.
+static gp_status upload_table(gp_plan *p, AxisPlan &A, const std::vector<std::complex<long double>> &c, bool conj,
+                              void **dst)
+{
+    const int64_t rows = A.npad + 1;
+    hipError_t e;
+    gp_status st;
+    if (p->prec == GP_C128) {
+        std::vector<double> h;
+        table_rows<double>(c, rows, A.r, p->mode, conj, h);
+        st = alloc(dst, h.size() * sizeof(double), p->device_bytes);
+        if (st != GP_OK) return st;
+        e = hipMemcpy(*dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> h;
+        table_rows<float>(c, rows, A.r, p->mode, conj, h);
+        st = alloc(dst, h.size() * sizeof(float), p->device_bytes);
+        if (st != GP_OK) return st;
+        e = hipMemcpy(*dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(table)");
+    return GP_OK;
+}
+
+static void free_plan(gp_plan *p)
+{
+    if (!p) return;
+    for (int a = 0; a < 3; ++a) {
+        if (p->ax[a].d_tab) hipFree(p->ax[a].d_tab);
+        if (p->ax[a].d_tab_adj) hipFree(p->ax[a].d_tab_adj);
+    }
+    if (p->d_norm) hipFree(p->d_norm);
+    if (p->d_adj) hipFree(p->d_adj);
+    if (p->d_obs) hipFree(p->d_obs);
+    for (hipEvent_t e : p->timing.ev) hipEventDestroy(e);
+    delete p;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace gp
+
+using namespace gp;
+
+extern "C" {
+
+const char *gp_strerror(gp_status s)
+{
+    switch (s) {
+    case GP_OK: return "ok";
+    case GP_EINVAL: return "invalid argument";
+    case GP_ENOMEM: return "out of memory";
+    case GP_EHIP: return "HIP runtime error";
+    case GP_ENONFINITE: return "non-finite result";
+    case GP_EUNSUPPORTED: return "unsupported";
+    case GP_ETIMEOUT: return "device wait timed out";
+    }
+    return "unknown status";
+}
+
+const char *gp_last_error(void) { return g_last_error.c_str(); }
+
+const char *gp_kernel_name(int kind)
+{
+    static const char *names[GP_NUM_KERNEL_KINDS] = {
+        "sweep_x", "sweep_y", "sweep_z", "sweep_exact", "scale", "observables",
+        "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy"};
+    if (kind < 0 || kind >= GP_NUM_KERNEL_KINDS) return "unknown";
+    return names[kind];
+}
+
+gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt, gp_mode mode,
+                         const gp_trap *trap, double g, gp_prec prec)
+{
+    if (!out) return set_error("out is NULL"), GP_EINVAL;
+    *out = nullptr;
+    if (ndim < 1 || ndim > 3) return set_error("ndim must be 1, 2 or 3"), GP_EINVAL;
+    if (!n || !dx) return set_error("n or dx is NULL"), GP_EINVAL;
+    for (int a = 0; a < ndim; ++a) {
+        if (n[a] < 1) return set_error("grid size must be >= 1"), GP_EINVAL;
+        if (!finite_pos(dx[a])) return set_error("dx must be finite and > 0"), GP_EINVAL;
+    }
+    if (!finite_pos(dt)) return set_error("dt must be finite and > 0"), GP_EINVAL;
+    if (mode != GP_IMAG && mode != GP_REAL) return set_error("bad mode"), GP_EINVAL;
+    if (prec != GP_C128 && prec != GP_C64) return set_error("bad precision"), GP_EINVAL;
+    if (!std::isfinite(g)) return set_error("g must be finite"), GP_EINVAL;
+    int64_t npts = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (n[a] > ((int64_t)1 << 31) || npts > ((int64_t)1 << 40) / n[a])
+            return set_error("grid too large"), GP_EINVAL;
+        npts *= n[a];
+    }
+    if (trap) {
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(trap->omega[a])) return set_error("omega must be finite"), GP_EINVAL;
+        if (trap->sched_len < 0 || (trap->sched_len > 0 && !trap->omega_sched))
+            return set_error("bad trap schedule"), GP_EINVAL;
+        if (trap->sched_len > 0 && (trap->sched_axis < 0 || trap->sched_axis >= ndim))
+            return set_error("schedule axis out of range"), GP_EINVAL;
+        for (int64_t k = 0; k < trap->sched_len; ++k)
+            if (!std::isfinite(trap->omega_sched[k])) return set_error("schedule value not finite"), GP_EINVAL;
+    }
+
+    gp_plan *p = new (std::nothrow) gp_plan();
+    if (!p) return set_error("host allocation failed"), GP_ENOMEM;
+    p->ndim = ndim;
+    p->dt = dt;
+    p->mode = mode;
+    p->prec = prec;
+    p->g = g;
+    p->npts = npts;
+    p->dV = 1.0;
+    for (int a = 0; a < ndim; ++a) {
+        p->n[a] = n[a];
+        p->dx[a] = dx[a];
+        p->dV *= dx[a];
+    }
+    if (trap) {
+        for (int a = 0; a < ndim; ++a) p->omega[a] = trap->omega[a];
+        if (trap->sched_len > 0) p->sched.assign(trap->omega_sched, trap->omega_sched + trap->sched_len);
+        p->sched_axis = trap->sched_len > 0 ? trap->sched_axis : 0;
+    }
+
+    // host-side plan of each axis: line addressing, tables, window
+    const int64_t nx = p->n[0], ny = p->n[1];
+    std::vector<std::complex<long double>> cs[3];
+    for (int a = 0; a < ndim; ++a) {
+        AxisPlan &A = p->ax[a];
+        A.n = n[a];
+        A.nlines = npts / n[a];
+        if (a == 0) {  // line l = j + ny k -> first element l * nx, stride 1
+            A.stride = 1;
+            A.m1 = 1;
+            A.s1 = 0;
+            A.s2 = nx;
+        } else if (a == 1) {  // line l = i + nx k -> i + nx ny k, stride nx
+            A.stride = nx;
+            A.m1 = nx;
+            A.s1 = 1;
+            A.s2 = nx * ny;
+        } else {  // line l = i + nx j -> l, stride nx ny
+            A.stride = nx * ny;
+            A.m1 = A.nlines;
+            A.s1 = 1;
+            A.s2 = 0;
+        }
+        A.r = dt / (4.0 * dx[a] * dx[a]);
+        thomas_c(A.n, A.r, mode, cs[a], A.rho);
+        choose_window(A, prec);
+    }
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    gp_status st = GP_OK;
+    for (int a = 0; a < ndim && st == GP_OK; ++a) {
+        st = upload_table(p, p->ax[a], cs[a], false, &p->ax[a].d_tab);
+        if (st == GP_OK && mode == GP_REAL) st = upload_table(p, p->ax[a], cs[a], true, &p->ax[a].d_tab_adj);
+    }
+    int64_t maxg = 1;
+    for (int a = 0; a < ndim; ++a) maxg = std::max(maxg, sweep_groups(p, a));
+    p->n_norm = maxg;
+    p->n_adj = maxg;
+    p->n_obs_blocks = obs_groups(p);
+    if (st == GP_OK) st = alloc((void **)&p->d_norm, 2 * maxg * sizeof(double), p->device_bytes);
+    if (st == GP_OK) st = alloc((void **)&p->d_adj, 2 * maxg * sizeof(double), p->device_bytes);
+    if (st == GP_OK)
+        st = alloc((void **)&p->d_obs, (p->n_obs_blocks + 1) * kObsFields * sizeof(double), p->device_bytes);
+    if (st != GP_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return GP_OK;
+}
+
+gp_status gp_plan_destroy(gp_plan *plan)
+{
+    free_plan(plan);
+    return GP_OK;
+}
+
+gp_status gp_plan_set_step(gp_plan *plan, int64_t step)
+{
+    if (!plan || step < 0) return set_error("bad plan or step"), GP_EINVAL;
+    plan->step = step;
+    return GP_OK;
+}
+
+gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info)
+{
+    if (!plan || !info) return set_error("NULL argument"), GP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->ndim = plan->ndim;
+    for (int a = 0; a < 3; ++a) {
+        info->n[a] = a < plan->ndim ? plan->n[a] : 1;
+        info->window[a] = a < plan->ndim ? plan->ax[a].K : 0;
+        info->rho[a] = a < plan->ndim ? plan->ax[a].rho : 0.0;
+        info->window_bound[a] = a < plan->ndim ? plan->ax[a].bound : 0.0;
+    }
+    info->step = plan->step;
+    info->device_bytes = plan->device_bytes;
+    return GP_OK;
+}
+
+gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec prec, int adjoint, double *c,
+                          double *beta, int *window, double *rho)
+{
+    if (n < 1 || n > ((int64_t)1 << 31) || !finite_pos(dx) || !finite_pos(dt) || !c || !beta || !window || !rho)
+        return set_error("bad argument"), GP_EINVAL;
+    if (mode != GP_IMAG && mode != GP_REAL) return set_error("bad mode"), GP_EINVAL;
+    if (prec != GP_C128 && prec != GP_C64) return set_error("bad precision"), GP_EINVAL;
+    AxisPlan A;
+    A.n = n;
+    A.r = dt / (4.0 * dx * dx);
+    std::vector<std::complex<long double>> cs;
+    thomas_c(n, A.r, mode, cs, A.rho);
+    choose_window(A, prec);
+    const int64_t rows = n + 1;
+    auto emit = [&](auto &h) {
+        for (int64_t q = 0; q < n; ++q) {
+            const auto *row = &h[6 * (q + 1)];
+            c[2 * q] = (double)row[0];
+            c[2 * q + 1] = (double)row[1];
+            beta[2 * q] = (double)row[2];
+            beta[2 * q + 1] = (double)row[3] + (double)row[4];
+        }
+    };
+    if (prec == GP_C128) {
+        std::vector<double> h;
+        table_rows<double>(cs, rows, A.r, mode, adjoint != 0, h);
+        emit(h);
+    } else {
+        std::vector<float> h;
+        table_rows<float>(cs, rows, A.r, mode, adjoint != 0, h);
+        emit(h);
+    }
+    *window = A.K;
+    *rho = A.rho;
+    return GP_OK;
+}
+
+gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
+{
+    if (!p || !psi || nsteps < 0) return set_error("bad plan, psi or nsteps"), GP_EINVAL;
+    if (nsteps == 0) return GP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const bool imag = p->mode == GP_IMAG;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = p->step + k;
+        for (int a = 0; a < p->ndim; ++a) {
+            int flags = 0;
+            if (a == 0) flags |= F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
+            if (imag && a == p->ndim - 1) flags |= F_NORM_OUT;
+            e = launch_sweep(p, a, psi, flags, false, n, nullptr, s);
+            if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        }
+    }
+    p->step += nsteps;
+    if (imag) {
+        e = launch_scale(p, psi, s);
+        if (e != hipSuccess) return hip_fail(e, "scale launch");
+    }
+    return GP_OK;
+}
+
+gp_status gp_observables(gp_plan *p, const void *psi, gp_obs *out, void *stream)
+{
+    if (!p || !psi || !out) return set_error("NULL argument"), GP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = launch_observables(p, psi, s);
+    if (e != hipSuccess) return hip_fail(e, "observables launch");
+    double f[kObsFields];
+    e = hipMemcpyAsync(f, p->d_obs + p->n_obs_blocks * kObsFields, sizeof(f), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(observables)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const double dv = p->dV;
+    out->norm = dv * f[0];
+    out->epot = dv * f[1];
+    out->eint = 0.5 * p->g * dv * f[2];
+    out->ekin = 0.0;
+    for (int a = 0; a < p->ndim; ++a) out->ekin += 0.5 * dv * f[6 + a] / (p->dx[a] * p->dx[a]);
+    out->energy = out->ekin + out->epot + out->eint;
+    out->mu = out->ekin + out->epot + 2.0 * out->eint;
+    for (int a = 0; a < 3; ++a) out->rms[a] = a < p->ndim ? std::sqrt(dv * f[3 + a] / out->norm) : 0.0;
+    if (!std::isfinite(out->norm) || !std::isfinite(out->energy)) {
+        set_error("non-finite norm or energy");
+        return GP_ENONFINITE;
+    }
+    return GP_OK;
+}
+
+gp_status gp_step_adjoint(gp_plan *p, const void *states, void *lambda, int64_t n_first, int64_t nsteps,
+                          double *dsched, double *dg, void *stream)
+{
+    if (!p || !states || !lambda || nsteps < 0 || n_first < 0) return set_error("bad argument"), GP_EINVAL;
+    if (p->mode != GP_REAL) return set_error("adjoint needs a real-time plan"), GP_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t bytes = (size_t)p->npts * elem_bytes(p->prec);
+    const int64_t nparts = sweep_groups(p, 0);
+    for (int64_t k = nsteps - 1; k >= 0; --k) {
+        const int64_t n = n_first + k;
+        const void *st = (const char *)states + (size_t)k * bytes;
+        for (int a = p->ndim - 1; a >= 0; --a) {
+            e = launch_sweep(p, a, lambda, a == 0 ? F_ADJ_N : 0, true, n, st, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint sweep launch");
+        }
+        double w[3];
+        omega_at_step(p, n, w);
+        const double coeff = p->dt * w[p->sched_axis];
+        e = launch_adj_reduce(p, nparts, coeff, dsched ? dsched + k : nullptr, dg, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint reduce launch");
+    }
+    return GP_OK;
+}
+
+gp_status gp_plan_timing_enable(gp_plan *p, int64_t capacity)
+{
+    if (!p || capacity < 0) return set_error("bad argument"), GP_EINVAL;
+    Timing &T = p->timing;
+    for (hipEvent_t ev : T.ev) hipEventDestroy(ev);
+    T.ev.clear();
+    T.kind.clear();
+    T.used = 0;
+    T.capacity = 0;
+    if (capacity == 0) return GP_OK;
+    T.ev.resize(2 * capacity);
+    T.kind.resize(capacity);
+    for (int64_t i = 0; i < 2 * capacity; ++i) {
+        hipError_t e = hipEventCreate(&T.ev[i]);
+        if (e != hipSuccess) {
+            T.ev.resize(i);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    T.capacity = capacity;
+    return GP_OK;
+}
+
+gp_status gp_plan_timing_read(gp_plan *p, int64_t *counts, double *total_ms)
+{
+    if (!p || !counts || !total_ms) return set_error("bad argument"), GP_EINVAL;
+    for (int k = 0; k < GP_NUM_KERNEL_KINDS; ++k) {
+        counts[k] = 0;
+        total_ms[k] = 0.0;
+    }
+    Timing &T = p->timing;
+    if (T.used > 0) {
+        hipError_t e = hipEventSynchronize(T.ev[2 * T.used - 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    for (int64_t i = 0; i < T.used; ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        counts[T.kind[i]] += 1;
+        total_ms[T.kind[i]] += ms;
+    }
+    T.used = 0;
+    return GP_OK;
+}
+
+gp_status gp_copy_probe(void *dst, const void *src, int64_t bytes, void *stream)
+{
+    if (!dst || !src || bytes <= 0 || bytes % 16) return set_error("bad copy arguments"), GP_EINVAL;
+    hipError_t e = launch_copy(dst, src, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return GP_OK;
+}
+
+}  // extern "C"

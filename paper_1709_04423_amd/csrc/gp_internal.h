@@ -1,0 +1,146 @@
+// Internal declarations of libgp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gp.h"
+
+namespace gp {
+
+// Kinds of kernel launches, for per-kernel timing.
+enum KernelKind {
+    K_SWEEP_X = 0,
+    K_SWEEP_Y = 1,
+    K_SWEEP_Z = 2,
+    K_SWEEP_EXACT = 3,
+    K_SCALE = 4,
+    K_OBS = 5,
+    K_OBS_FINAL = 6,
+    K_ADJ_X = 7,
+    K_ADJ_YZ = 8,
+    K_ADJ_REDUCE = 9,
+    K_BATCH = 10,
+    K_COPY = 11,
+};
+
+// Flags of the line-sweep kernel.
+enum SweepFlags {
+    F_FUSE_N = 1,   // potential + nonlinear substep applied to every value at load (axis 0)
+    F_RENORM = 2,   // scale loaded values by 1/sqrt(dV * sum of norm partials) first
+    F_NORM_OUT = 4, // write an FP64 per-workgroup partial of sum |u'|^2
+    F_ADJ_N = 8,    // adjoint of the potential substep applied at store (axis 0)
+};
+
+constexpr int kLanes = 64;      // one wavefront = one workgroup of the sweeps
+constexpr int kBlock = 16;      // points per block of the streaming line solver
+constexpr int kMaxLdsBytes = 64 * 1024;
+
+// Everything a sweep launch needs; passed by value as the kernel argument.
+struct SweepParams {
+    void *psi;            // in/out grid
+    const void *state;    // F_ADJ_N: input state of the step being reversed
+    int64_t n;            // line length
+    int64_t stride;       // element stride along the line
+    int64_t nlines;       // number of lines
+    int64_t m1, s1, s2;   // first element of line l: (l % m1) * s1 + (l / m1) * s2
+    const void *tab;      // Thomas table rows p = -1 .. npad-1: c'_p, beta_p, beta_p lo (precision of psi)
+    int K;                // back-substitution window
+    int lmask;            // ring slots - 1 (power of two)
+    int D;                // output delay in blocks: ceil((K + 1) / kBlock)
+    int nblocks;          // ceil(n / kBlock)
+    // potential substep on axis 0
+    double dt, g;
+    double hw2[3];        // 1/2 omega_a^2 of this step
+    double x0[3], dx[3];  // coordinate of index i on axis a: (i + x0[a]) * dx[a]
+    int64_t ny;           // axis-0 line index l -> (j, k) = (l % ny, l / ny)
+    int sched_axis;       // F_ADJ_N: axis whose x^2 weights the schedule gradient
+    // imaginary-time renormalisation
+    const double *norm_in;
+    int nnorm_in;
+    double dV;
+    double *norm_out;     // F_NORM_OUT partials, one per workgroup
+    double *adj_out;      // F_ADJ_N partials, two per workgroup
+};
+
+struct AxisPlan {
+    int64_t n = 1, stride = 1, nlines = 1, m1 = 1, s1 = 0, s2 = 0;
+    double r = 0.0;
+    double rho = 0.0;
+    int K = 0;            // window; -1 = exact two-pass solver
+    int D = 0, L = 0;
+    int64_t npad = 0;     // table rows after the p = -1 row
+    double bound = 0.0;
+    std::vector<double> c;             // FP64 c'_p (interleaved complex), before rounding
+    void *d_tab = nullptr;             // device table (forward)
+    void *d_tab_adj = nullptr;         // device table (conjugate)
+};
+
+struct Timing {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    int64_t used = 0;
+    int64_t capacity = 0;
+};
+
+}  // namespace gp
+
+struct gp_plan {
+    int ndim = 1;
+    int64_t n[3] = {1, 1, 1};
+    double dx[3] = {1.0, 1.0, 1.0};
+    double dt = 0.0;
+    gp_mode mode = GP_IMAG;
+    gp_prec prec = GP_C128;
+    double g = 0.0;
+    double omega[3] = {0.0, 0.0, 0.0};
+    std::vector<double> sched;
+    int sched_axis = 0;
+    int64_t step = 0;
+    int64_t npts = 1;
+    double dV = 1.0;
+    int device = 0;
+    gp::AxisPlan ax[3];
+    double *d_norm = nullptr;       // norm partials of the last sweep
+    int64_t n_norm = 0;
+    double *d_adj = nullptr;        // adjoint partials (2 per workgroup)
+    int64_t n_adj = 0;
+    double *d_obs = nullptr;        // observable partials + final sums
+    int64_t n_obs_blocks = 0;
+    int64_t device_bytes = 0;
+    gp::Timing timing;
+};
+
+namespace gp {
+
+void set_error(const std::string &msg);
+gp_status hip_fail(hipError_t e, const char *what);
+
+// Launch helpers (stream-ordered, asynchronous).
+void timing_begin(gp_plan *p, int kind, hipStream_t s);
+void timing_end(gp_plan *p, hipStream_t s);
+
+size_t elem_bytes(gp_prec prec);
+double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
+
+// Sweep along one axis; flags per SweepFlags; adjoint selects the conjugate map.
+hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint, int64_t step_index,
+                        const void *state, hipStream_t s);
+hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
+hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
+hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,
+                             double *dg, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);
+
+// Number of workgroups a sweep along `axis` launches.
+int64_t sweep_groups(const gp_plan *p, int axis);
+int64_t obs_groups(const gp_plan *p);
+constexpr int kObsFields = 10;
+constexpr int kObsThreads = 256;
+
+void omega_at_step(const gp_plan *p, int64_t step, double w[3]);
+
+}  // namespace gp

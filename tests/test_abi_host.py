@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol that
+include/gp.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1709_04423_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_header_is_plain_c():
+    # the boundary takes plain pointers and sizes: no torch or HIP types in it
+    text = open(os.path.join(ROOT, "include", "gp.h")).read()
+    code = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    for word in ("torch", "at::", "hipStream_t", "#include <hip", "std::"):
+        assert word not in code
+
+
+def test_status_strings():
+    L = binding.lib()
+    assert L.gp_strerror(binding.GP_EINVAL) == b"invalid argument"
+    assert L.gp_strerror(binding.GP_OK) == b"ok"
+    assert binding.kernel_names()[0] == "sweep_x"
+
+
+def _create(ndim, n, dx, dt, mode=0, prec=0, g=0.0, trap=None):
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    n_arr = (ctypes.c_int64 * max(ndim, 1))(*n) if n is not None else None
+    dx_arr = (ctypes.c_double * max(ndim, 1))(*dx) if dx is not None else None
+    st = L.gp_plan_create(ctypes.byref(h), ndim, n_arr, dx_arr, dt, mode,
+                          ctypes.byref(trap) if trap is not None else None, g, prec)
+    return st, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, [4], [0.1], 0.01),            # ndim
+    (4, [4, 4, 4, 4], [0.1] * 4, 0.01),
+    (1, [0], [0.1], 0.01),            # empty axis
+    (1, [-3], [0.1], 0.01),
+    (1, [8], [0.0], 0.01),            # dx
+    (1, [8], [-0.1], 0.01),
+    (1, [8], [float("nan")], 0.01),
+    (1, [8], [0.1], 0.0),             # dt
+    (1, [8], [0.1], -1e-3),
+    (1, [8], [0.1], float("inf")),
+    (2, [1 << 32, 8], [0.1, 0.1], 0.01),  # too large
+])
+def test_plan_create_rejects_bad_geometry(args):
+    st, h = _create(*args)
+    assert st == binding.GP_EINVAL
+    assert not h.value
+
+
+def test_plan_create_rejects_bad_enums_and_trap():
+    assert _create(1, [8], [0.1], 0.01, mode=2)[0] == binding.GP_EINVAL
+    assert _create(1, [8], [0.1], 0.01, prec=7)[0] == binding.GP_EINVAL
+    assert _create(1, [8], [0.1], 0.01, g=float("nan"))[0] == binding.GP_EINVAL
+    t = binding.GpTrap()
+    t.sched_len = 3  # schedule length without an array
+    assert _create(1, [8], [0.1], 0.01, trap=t)[0] == binding.GP_EINVAL
+    arr = (ctypes.c_double * 3)(1.0, 1.1, 1.2)
+    t.omega_sched = ctypes.cast(arr, binding.c_dp)
+    t.sched_axis = 1  # axis beyond ndim = 1
+    assert _create(1, [8], [0.1], 0.01, trap=t)[0] == binding.GP_EINVAL
+    t.sched_axis = 0
+    t.omega[1] = float("inf")
+    assert _create(1, [8], [0.1], 0.01, trap=t)[0] == binding.GP_EINVAL
+    assert binding.lib().gp_plan_create(None, 1, None, None, 0.1, 0, None, 0.0, 0) == binding.GP_EINVAL
+
+
+def test_null_handles_are_rejected():
+    L = binding.lib()
+    obs = binding.GpObs()
+    assert L.gp_step(None, None, 1, None) == binding.GP_EINVAL
+    assert L.gp_observables(None, None, ctypes.byref(obs), None) == binding.GP_EINVAL
+    assert L.gp_plan_set_step(None, 0) == binding.GP_EINVAL
+    assert L.gp_plan_get_info(None, None) == binding.GP_EINVAL
+    assert L.gp_step_adjoint(None, None, None, 0, 1, None, None, None) == binding.GP_EINVAL
+    assert L.gp_plan_timing_enable(None, 4) == binding.GP_EINVAL
+    assert L.gp_copy_probe(None, None, 16, None) == binding.GP_EINVAL
+    assert L.gp_plan_destroy(None) == binding.GP_OK
+    assert L.gp_batch_destroy(None) == binding.GP_OK
+    h = ctypes.c_void_p()
+    assert L.gp_batch_create(ctypes.byref(h), 0, None, None, None, 1, None, None, 1) == binding.GP_EINVAL
+    assert L.gp_batch_step(None, None, 1, None) == binding.GP_EINVAL
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        binding.lib()

@@ -1,0 +1,136 @@
+"""Host checks of the precomputed Thomas tables (no GPU): they factor the
+Crank-Nicolson system correctly, the windowed back substitution the sweep
+kernels perform reproduces a dense solve, and in real time the rounded tables
+keep the map unitary."""
+import numpy as np
+import pytest
+
+from paper_1709_04423_amd import binding
+
+BLOCK = 16  # points per block of the streaming solver (kBlock in the kernels)
+
+
+def cn_dense(n, dx, dt, mode, adjoint=False):
+    r = dt / (4 * dx * dx)
+    b, e = (1 + 2j * r, -1j * r) if mode == binding.GP_REAL else (1 + 2 * r + 0j, -r + 0j)
+    if adjoint:
+        b, e = np.conj(b), np.conj(e)
+    A = np.diag(np.full(n, b)) + np.diag(np.full(n - 1, e), 1) + np.diag(np.full(n - 1, e), -1)
+    B = np.diag(np.full(n, 2 - b)) - np.diag(np.full(n - 1, e), 1) - np.diag(np.full(n - 1, e), -1)
+    return A, B
+
+
+def solve_with_table(c, beta, u):
+    """Full Thomas solve of the scaled system with the table (no window)."""
+    n = len(u)
+    up = np.concatenate([[0], u, [0]])
+    rhs = beta * u - (up[:-2] + up[2:])
+    y = np.zeros(n, complex)
+    prev = 0
+    for p in range(n):
+        y[p] = (rhs[p] - prev) * c[p]
+        prev = y[p]
+    v = np.zeros(n, complex)
+    nxt = 0
+    for p in range(n - 1, -1, -1):
+        v[p] = y[p] - c[p] * nxt
+        nxt = v[p]
+    return v
+
+
+def solve_windowed(c, beta, u, K):
+    """The kernels' streaming algorithm: blocks of BLOCK points, exact forward
+    elimination, back substitution per output block started K points past it
+    with zero, rows past the line zero."""
+    n = len(u)
+    D = (K + 1 + BLOCK - 1) // BLOCK
+    nblocks = (n + BLOCK - 1) // BLOCK
+    nit = nblocks + D
+    rows = nit * BLOCK + 1
+    ctab = np.zeros(rows, complex)
+    btab = np.zeros(rows, complex)
+    ctab[1:n + 1] = c
+    btab[1:n + 1] = beta
+    ext = np.zeros(nit * BLOCK + 2, complex)
+    ext[:n] = u
+    y = {}
+    out = np.zeros(n, complex)
+    um1 = u0 = yprev = 0
+    for j in range(nit):
+        for k in range(BLOCK):
+            q = j * BLOCK + k
+            up1 = ext[q]
+            rhs = btab[q] * u0 - (um1 + up1)
+            d = (rhs - yprev) * ctab[q]
+            y[q - 1] = d
+            yprev, um1, u0 = d, u0, up1
+        o = j - D
+        if o >= 0:
+            ob = o * BLOCK
+            v = 0
+            for t in range(ob + BLOCK - 1 + K, ob - 1, -1):
+                v = y[t] - ctab[t + 1] * v
+                if t < ob + BLOCK and t < n:
+                    out[t] = v
+    return out
+
+
+CASES = [(1, 0.05, 1e-3), (7, 0.1, 1e-2), (37, 0.2, 1e-2), (256, 0.05, 2e-4), (300, 0.05, 1e-3),
+         (128, 0.1, 1e-3), (50, 0.05, 3e-3)]
+
+
+@pytest.mark.parametrize("mode", [binding.GP_IMAG, binding.GP_REAL])
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("case", CASES)
+def test_table_factorises_cn_fp64(mode, adjoint, case):
+    n, dx, dt = case
+    if adjoint and mode == binding.GP_IMAG:
+        pytest.skip("the adjoint is defined for real time")
+    c, beta, K, rho = binding.thomas_table(n, dx, dt, mode, binding.GP_C128, adjoint)
+    A, B = cn_dense(n, dx, dt, mode, adjoint)
+    u = np.random.default_rng(n).standard_normal(n) + 1j * np.random.default_rng(n + 1).standard_normal(n)
+    ref = np.linalg.solve(A, B @ u)
+    got = solve_with_table(c, beta, u)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert K >= 0
+    win = solve_windowed(c, beta, u, K)
+    assert np.max(np.abs(win - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("mode", [binding.GP_IMAG, binding.GP_REAL])
+def test_table_fp32_rounding(mode):
+    n, dx, dt = 256, 0.05, 2e-4
+    c, beta, K, rho = binding.thomas_table(n, dx, dt, mode, binding.GP_C64)
+    assert np.all(c.real.astype(np.float32) == c.real) and np.all(c.imag.astype(np.float32) == c.imag)
+    A, B = cn_dense(n, dx, dt, mode)
+    u = np.random.default_rng(3).standard_normal(n) + 0j
+    ref = np.linalg.solve(A, B @ u)
+    got = solve_windowed(c, beta, u, K)
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+def test_real_time_fp32_table_is_unitary_in_the_interior():
+    # delta_p = 1/c'_p + c'_{p-1} of the rounded table: Im beta_p must equal Im delta_p
+    # to far better than FP32 precision, so that the map's Hermitian parts agree
+    n, dx, dt = 256, 0.05, 2e-4
+    c, beta, K, rho = binding.thomas_table(n, dx, dt, binding.GP_REAL, binding.GP_C64)
+    cl = c.astype(np.clongdouble)
+    delta = 1 / cl + np.concatenate([[0], cl[:-1]])
+    assert np.max(np.abs(beta.imag - delta.imag.astype(np.float64)) / np.abs(delta.imag)) < 1e-14
+    # plain rounding of Im beta to FP32 would leave ~1e-8; the map built from the
+    # FP32 values stays norm-preserving on a smooth interior mode to ~1e-13
+    A_eff = np.diag(delta.astype(complex)) + np.diag(np.ones(n - 1), 1) + np.diag(np.ones(n - 1), -1)
+    B_eff = np.diag(beta) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    x = np.arange(n) - n / 2
+    u = np.exp(-(x / 30.0) ** 2) + 0j
+    v = np.linalg.solve(A_eff, B_eff @ u)
+    assert abs(np.linalg.norm(v) / np.linalg.norm(u) - 1) < 1e-13
+
+
+def test_window_depth_and_exact_fallback():
+    _, _, K, rho = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C128)
+    assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and rho ** K > 2.0 ** -60
+    _, _, K32, _ = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C64)
+    assert K32 < K
+    _, _, Kx, rho_x = binding.thomas_table(64, 0.05, 0.2, binding.GP_REAL, binding.GP_C128)
+    assert Kx == -1 and rho_x > 0.8
