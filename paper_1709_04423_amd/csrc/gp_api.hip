@@ -102,7 +102,7 @@ static void table_rows(const std::vector<std::complex<long double>> &c, int64_t 
 // exact two-pass solver when the ring does not fit in LDS.
 static void choose_window(AxisPlan &A, gp_prec prec)
 {
-    const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -30);
+    const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
     int K = 0;
     double bound = A.rho;
     while (bound > tol && K < 100000) {

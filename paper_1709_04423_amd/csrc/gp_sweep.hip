@@ -15,7 +15,7 @@
 // u_t = y_t - c'_t u_{t+1} runs per output block of kBlock points, starting K
 // points past the block with u = 0: the neglected term is multiplied by
 // prod |c'| <= rho^(K+1) before it reaches an output, and the host picks K so
-// that rho^(K+1) is below 2^-60 (FP64) or 2^-30 (FP32).  Rows past the end of
+// that rho^(K+1) is below 2^-60 (FP64) or 2^-48 (FP32).  Rows past the end of
 // a line hold c' = 0, so the tail of every line is exact.  Each point is read
 // once and written once.  When the window does not fit in LDS, k_sweep_exact
 // runs the plain two-pass Thomas algorithm (eliminated values stored in
@@ -63,12 +63,16 @@ __device__ __forceinline__ cp<R> cn_rhs(cp<R> um1, cp<R> u, cp<R> up1, V beta, V
 {
     const R sr = um1.re + up1.re, si = um1.im + up1.im;
     if (MODE == GP_IMAG) return {beta.x * u.re - sr, beta.x * u.im - si};
+    // The small part (a discrete Laplacian plus the lo correction) is formed
+    // first and the large i Im(beta) u term added last: added after it, the lo
+    // correction would fall below that sum's rounding and be lost every time,
+    // which biases the norm by the rounding of Im(beta) per sweep.
     R re = beta.x * u.re - sr;
     R im = beta.x * u.im - si;
-    re -= beta.y * u.im;
-    im += beta.y * u.re;
     re -= beta_lo.x * u.im;
     im += beta_lo.x * u.re;
+    re -= beta.y * u.im;
+    im += beta.y * u.re;
     return {re, im};
 }
 
@@ -144,6 +148,24 @@ __device__ __forceinline__ LineCtx<R> line_setup(const SweepParams &P, int lane)
     return L;
 }
 
+// Per-line potential data of an axis-0 line given its index (transposed layout).
+template <typename R>
+__device__ __forceinline__ LineCtx<R> line_ctx_of(const SweepParams &P, int64_t line)
+{
+    LineCtx<R> L;
+    L.base = line * P.n;
+    L.active = true;
+    L.scale = 1.0;
+    const uint32_t l = (uint32_t)line, ny = (uint32_t)P.ny;
+    const double y = ((double)(l % ny) + P.x0[1]) * P.dx[1];
+    const double z = ((double)(l / ny) + P.x0[2]) * P.dx[2];
+    L.vperp = R(P.hw2[1] * y * y + P.hw2[2] * z * z);
+    L.hw0 = R(P.hw2[0]);
+    L.ysq = R(y * y);
+    L.zsq = R(z * z);
+    return L;
+}
+
 // Potential + nonlinear substep on one value at point q of an axis-0 line.
 template <typename R, int MODE, int FLAGS>
 __device__ __forceinline__ cp<R> potential_substep(cp<R> u, int64_t q, const SweepParams &P,
@@ -206,44 +228,91 @@ __device__ __forceinline__ void write_partials(const SweepParams &P, int lane, d
     }
 }
 
-// Streaming solver with a windowed back substitution (see the file header).
-template <typename R, int MODE, int FLAGS>
-__global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
-                                                         typename CT<R>::V *__restrict__ psi,
-                                                         const typename CT<R>::V *__restrict__ tab,
-                                                         const typename CT<R>::V *__restrict__ state)
-{
+// Access patterns of the windowed solver.
+//  kStrided: lane = line, point q of the line at base + q*stride; used for the
+//    y and z axes, whose 64 lines per wavefront are adjacent in memory, so each
+//    load/store instruction moves one contiguous row.
+//  kTransposed: the 64 lines of a wavefront are 64 consecutive x lines (length
+//    n, stride 1).  Each block of kBlock points of the 64 lines is loaded with
+//    coalesced instructions (instruction i, lane -> line 4i + lane/16, point
+//    lane%16) and transposed through an LDS tile to the one-line-per-lane layout
+//    of the solver; outputs go back the same way.
+enum Access { kStrided = 0, kTransposed = 1 };
+constexpr int kTilePitch = kBlock + 1;  // tile row pitch in values: conflict-free b128 access
+
+template <typename R, int MODE, int FLAGS, int ACC> struct WindowSweep {
     using V = typename CT<R>::V;
-    constexpr int B = kBlock;
-    extern __shared__ char lds_raw[];
-    V *ring = reinterpret_cast<V *>(lds_raw);
-    const int lane = threadIdx.x;
-    const LineCtx<R> L = line_setup<R, FLAGS>(P, lane);
-    const int64_t n = P.n, stride = P.stride, base = L.base;
-    const int lmask = P.lmask;
-    const int nit = P.nblocks + P.D;
-    const V zero = to_v<V>(cp<R>{R(0), R(0)});
+    static constexpr int B = kBlock;
+    const SweepParams &P;
+    V *__restrict__ psi;
+    const V *__restrict__ tab;
+    const V *__restrict__ state;
+    V *ring;
+    V *tile;
+    LineCtx<R> L;
+    int lane;
+    int64_t n, stride, base, l0;
+    int lmask;
+    cp<R> um1, u0, dprev;
+    double nacc, acc_w, acc_g;
 
-    V cur[B], nxt[B];
+    __device__ __forceinline__ WindowSweep(const SweepParams &P_, V *psi_, const V *tab_, const V *state_, char *lds)
+        : P(P_), psi(psi_), tab(tab_), state(state_)
+    {
+        lane = threadIdx.x;
+        L = line_setup<R, FLAGS>(P, lane);
+        n = P.n;
+        stride = P.stride;
+        base = L.base;
+        l0 = (int64_t)blockIdx.x * kLanes;
+        lmask = P.lmask;
+        ring = reinterpret_cast<V *>(lds);
+        tile = ring + (size_t)(lmask + 1) * kLanes;
+        um1 = u0 = dprev = cp<R>{R(0), R(0)};
+        nacc = acc_w = acc_g = 0.0;
+    }
+
+    __device__ __forceinline__ static V zero() { return to_v<V>(cp<R>{R(0), R(0)}); }
+
+    // Issue the loads of block j.
+    __device__ __forceinline__ void load(V (&buf)[B], int j) const
+    {
+        const int64_t q0 = (int64_t)j * B;
+        if (ACC == kStrided) {
 #pragma unroll
-    for (int k = 0; k < B; ++k) cur[k] = (L.active && k < n) ? psi[base + (int64_t)k * stride] : zero;
-
-    cp<R> um1 = {R(0), R(0)}, u0 = {R(0), R(0)}, dprev = {R(0), R(0)};
-    double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
-
-    for (int j = 0; j < nit; ++j) {
-        // prefetch the next block while this one is eliminated
-        if (j + 1 < nit) {
-            const int64_t q0 = (int64_t)(j + 1) * B;
+            for (int k = 0; k < B; ++k) buf[k] = (L.active && q0 + k < n) ? psi[base + (q0 + k) * stride] : zero();
+        } else {
+            const int pt = lane & (B - 1);
+            const int64_t q = q0 + pt;
 #pragma unroll
-            for (int k = 0; k < B; ++k)
-                nxt[k] = (L.active && q0 + k < n) ? psi[base + (q0 + k) * stride] : zero;
+            for (int i = 0; i < B; ++i) {
+                const int64_t line = l0 + i * (kLanes / B) + lane / B;
+                buf[i] = (line < P.nlines && q < n) ? psi[line * n + q] : zero();
+            }
         }
-        // forward elimination of points p = jB-1 .. jB+B-2 (u_{p+1} = cur[k])
+    }
+
+    // Solve block j (values in buf) and write output block j - D.
+    __device__ __forceinline__ void process(V (&buf)[B], int j)
+    {
+        V own[B];
+        if (ACC == kTransposed) {
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                tile[(i * (kLanes / B) + lane / B) * kTilePitch + (lane & (B - 1))] = buf[i];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < B; ++k) own[k] = tile[lane * kTilePitch + k];
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int k = 0; k < B; ++k) own[k] = buf[k];
+        }
+        // forward elimination of points p = jB-1 .. jB+B-2 (u_{p+1} = own[k])
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int64_t q = (int64_t)j * B + k;
-            cp<R> up1 = from_v<R>(cur[k]);
+            cp<R> up1 = from_v<R>(own[k]);
             if ((FLAGS & F_FUSE_N) && q < n) up1 = potential_substep<R, MODE, FLAGS>(up1, q, P, L);
             const cp<R> rhs = cn_rhs<MODE, R>(um1, u0, up1, tab[3 * q + 1], tab[3 * q + 2]);  // row p+1 = q
             const cp<R> d = cn_elim<MODE, R>(rhs, dprev, tab[3 * q]);
@@ -254,18 +323,19 @@ __global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
         }
         // back substitution of output block o = j - D
         const int o = j - P.D;
-        if (o >= 0) {
-            const int64_t ob = (int64_t)o * B;
-            cp<R> v = {R(0), R(0)};
-            for (int64_t t = ob + B - 1 + P.K; t >= ob + B; --t)
-                v = cn_back<MODE, R>(from_v<R>(ring[(int)((t + 1) & lmask) * kLanes + lane]), tab[3 * (t + 1)], v);
-            cp<R> out[B];
+        if (o < 0) return;
+        const int64_t ob = (int64_t)o * B;
+        cp<R> v = {R(0), R(0)};
+        for (int64_t t = ob + B - 1 + P.K; t >= ob + B; --t)
+            v = cn_back<MODE, R>(from_v<R>(ring[(int)((t + 1) & lmask) * kLanes + lane]), tab[3 * (t + 1)], v);
+        cp<R> out[B];
 #pragma unroll
-            for (int k = B - 1; k >= 0; --k) {
-                const int64_t t = ob + k;
-                v = cn_back<MODE, R>(from_v<R>(ring[(int)((t + 1) & lmask) * kLanes + lane]), tab[3 * (t + 1)], v);
-                out[k] = v;
-            }
+        for (int k = B - 1; k >= 0; --k) {
+            const int64_t t = ob + k;
+            v = cn_back<MODE, R>(from_v<R>(ring[(int)((t + 1) & lmask) * kLanes + lane]), tab[3 * (t + 1)], v);
+            out[k] = v;
+        }
+        if (ACC == kStrided) {
 #pragma unroll
             for (int k = 0; k < B; ++k) {
                 const int64_t t = ob + k;
@@ -278,16 +348,65 @@ __global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
                     if (L.active) psi[addr] = to_v<V>(w);
                 }
             }
-        }
+        } else {
 #pragma unroll
-        for (int k = 0; k < B; ++k) cur[k] = nxt[k];
+            for (int k = 0; k < B; ++k) tile[lane * kTilePitch + k] = to_v<V>(out[k]);
+            __syncthreads();
+            const int pt = lane & (B - 1);
+            const int64_t t = ob + pt;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int lo = i * (kLanes / B) + lane / B;
+                const int64_t line = l0 + lo;
+                cp<R> w = from_v<R>(tile[lo * kTilePitch + pt]);
+                if (line < P.nlines && t < n) {
+                    const int64_t addr = line * n + t;
+                    if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
+                    if (FLAGS & F_ADJ_N) {
+                        const LineCtx<R> Lw = line_ctx_of<R>(P, line);
+                        w = potential_adjoint<R, MODE, FLAGS>(w, t, state, addr, P, Lw, acc_w, acc_g);
+                    }
+                    psi[addr] = to_v<V>(w);
+                }
+            }
+            __syncthreads();
+        }
     }
-    if (!L.active) {
-        nacc = 0.0;
-        acc_w = 0.0;
-        acc_g = 0.0;
+
+    __device__ __forceinline__ void finish()
+    {
+        if (ACC == kStrided && !L.active) {
+            nacc = 0.0;
+            acc_w = 0.0;
+            acc_g = 0.0;
+        }
+        write_partials<R, FLAGS>(P, lane, nacc, acc_w, acc_g);
     }
-    write_partials<R, FLAGS>(P, lane, nacc, acc_w, acc_g);
+};
+
+// Streaming solver with a windowed back substitution (see the file header).
+// The block loop is unrolled by two over ping-pong buffers, so the loads of
+// block j+1 stay in flight while block j is solved.
+template <typename R, int MODE, int FLAGS, int ACC>
+__global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
+                                                         typename CT<R>::V *__restrict__ psi,
+                                                         const typename CT<R>::V *__restrict__ tab,
+                                                         const typename CT<R>::V *__restrict__ state)
+{
+    using V = typename CT<R>::V;
+    extern __shared__ char lds_raw[];
+    WindowSweep<R, MODE, FLAGS, ACC> S(P, psi, tab, state, lds_raw);
+    const int nit = P.nblocks + P.D;
+    V a[kBlock], b[kBlock];
+    S.load(a, 0);
+    for (int j = 0; j < nit; j += 2) {
+        if (j + 1 < nit) S.load(b, j + 1);
+        S.process(a, j);
+        if (j + 1 >= nit) break;
+        if (j + 2 < nit) S.load(a, j + 2);
+        S.process(b, j + 1);
+    }
+    S.finish();
 }
 
 // Plain two-pass Thomas algorithm: forward elimination stores d in place,
@@ -337,7 +456,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
 // -------------------------------------------------------------- dispatch
 
 template <typename R, int MODE, int FLAGS>
-static hipError_t launch_one(const AxisPlan &A, const SweepParams &P, bool exact, const void *tab,
+static hipError_t launch_one(const AxisPlan &A, const SweepParams &P, bool exact, bool transposed, const void *tab,
                              hipStream_t s)
 {
     using V = typename CT<R>::V;
@@ -345,34 +464,38 @@ static hipError_t launch_one(const AxisPlan &A, const SweepParams &P, bool exact
     if (exact) {
         hipLaunchKernelGGL((k_sweep_exact<R, MODE, FLAGS>), dim3(grid), dim3(kLanes), 0, s, P,
                            (V *)P.psi, (const V *)tab, (const V *)P.state);
+    } else if (transposed) {
+        const size_t lds = ((size_t)A.L * kLanes + (size_t)kLanes * kTilePitch) * sizeof(V);
+        hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, kTransposed>), dim3(grid), dim3(kLanes), lds, s, P,
+                           (V *)P.psi, (const V *)tab, (const V *)P.state);
     } else {
         const size_t lds = (size_t)A.L * kLanes * sizeof(V);
-        hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS>), dim3(grid), dim3(kLanes), lds, s, P,
+        hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, kStrided>), dim3(grid), dim3(kLanes), lds, s, P,
                            (V *)P.psi, (const V *)tab, (const V *)P.state);
     }
     return hipGetLastError();
 }
 
 template <typename R, int MODE>
-static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int flags, bool exact,
+static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int flags, bool exact, bool tr,
                                  const void *tab, hipStream_t s)
 {
     if (MODE == GP_IMAG) {
         switch (flags) {
-        case 0: return launch_one<R, MODE, 0>(A, P, exact, tab, s);
-        case F_FUSE_N: return launch_one<R, MODE, F_FUSE_N>(A, P, exact, tab, s);
-        case F_FUSE_N | F_RENORM: return launch_one<R, MODE, F_FUSE_N | F_RENORM>(A, P, exact, tab, s);
-        case F_NORM_OUT: return launch_one<R, MODE, F_NORM_OUT>(A, P, exact, tab, s);
-        case F_FUSE_N | F_NORM_OUT: return launch_one<R, MODE, F_FUSE_N | F_NORM_OUT>(A, P, exact, tab, s);
+        case 0: return launch_one<R, MODE, 0>(A, P, exact, tr, tab, s);
+        case F_FUSE_N: return launch_one<R, MODE, F_FUSE_N>(A, P, exact, tr, tab, s);
+        case F_FUSE_N | F_RENORM: return launch_one<R, MODE, F_FUSE_N | F_RENORM>(A, P, exact, tr, tab, s);
+        case F_NORM_OUT: return launch_one<R, MODE, F_NORM_OUT>(A, P, exact, tr, tab, s);
+        case F_FUSE_N | F_NORM_OUT: return launch_one<R, MODE, F_FUSE_N | F_NORM_OUT>(A, P, exact, tr, tab, s);
         case F_FUSE_N | F_RENORM | F_NORM_OUT:
-            return launch_one<R, MODE, F_FUSE_N | F_RENORM | F_NORM_OUT>(A, P, exact, tab, s);
+            return launch_one<R, MODE, F_FUSE_N | F_RENORM | F_NORM_OUT>(A, P, exact, tr, tab, s);
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (flags) {
-        case 0: return launch_one<R, MODE, 0>(A, P, exact, tab, s);
-        case F_FUSE_N: return launch_one<R, MODE, F_FUSE_N>(A, P, exact, tab, s);
-        case F_ADJ_N: return launch_one<R, MODE, F_ADJ_N>(A, P, exact, tab, s);
+        case 0: return launch_one<R, MODE, 0>(A, P, exact, tr, tab, s);
+        case F_FUSE_N: return launch_one<R, MODE, F_FUSE_N>(A, P, exact, tr, tab, s);
+        case F_ADJ_N: return launch_one<R, MODE, F_ADJ_N>(A, P, exact, tr, tab, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -424,6 +547,9 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     P.norm_out = p->d_norm + parity * p->n_norm;
     P.adj_out = p->d_adj;
     const bool exact = A.K < 0;
+    // x lines are contiguous: coalesce through the LDS tile when ring + tile fit
+    const size_t tr_lds = ((size_t)A.L * kLanes + (size_t)kLanes * kTilePitch) * elem_bytes(p->prec);
+    const bool tr = axis == 0 && tr_lds <= (size_t)kMaxLdsBytes;
     const void *tab = adjoint ? A.d_tab_adj : A.d_tab;
     int kind = exact ? K_SWEEP_EXACT : (axis == 0 ? K_SWEEP_X : (axis == 1 ? K_SWEEP_Y : K_SWEEP_Z));
     if (flags & F_ADJ_N) kind = K_ADJ_X;
@@ -431,11 +557,11 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     timing_begin(p, kind, s);
     hipError_t e;
     if (p->prec == GP_C128)
-        e = p->mode == GP_IMAG ? dispatch_flags<double, GP_IMAG>(A, P, flags, exact, tab, s)
-                               : dispatch_flags<double, GP_REAL>(A, P, flags, exact, tab, s);
+        e = p->mode == GP_IMAG ? dispatch_flags<double, GP_IMAG>(A, P, flags, exact, tr, tab, s)
+                               : dispatch_flags<double, GP_REAL>(A, P, flags, exact, tr, tab, s);
     else
-        e = p->mode == GP_IMAG ? dispatch_flags<float, GP_IMAG>(A, P, flags, exact, tab, s)
-                               : dispatch_flags<float, GP_REAL>(A, P, flags, exact, tab, s);
+        e = p->mode == GP_IMAG ? dispatch_flags<float, GP_IMAG>(A, P, flags, exact, tr, tab, s)
+                               : dispatch_flags<float, GP_REAL>(A, P, flags, exact, tr, tab, s);
     timing_end(p, s);
     return e;
 }
