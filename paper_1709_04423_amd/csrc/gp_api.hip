@@ -98,28 +98,31 @@ static void table_rows(const std::vector<std::complex<long double>> &c, int64_t 
     }
 }
 
-// Window K (smallest K with rho^(K+1) <= tol), ring geometry, or -1 for the
-// exact two-pass solver when the ring does not fit in LDS.
+// Window: D = ceil((Kmin + 1) / kBlock) for the smallest Kmin with
+// rho^(Kmin+1) <= tol, used as K = D kBlock - 1 (the back substitution then
+// starts at the newest eliminated point); ring of next_pow2((D+1) kBlock)
+// slots.  K = -1 selects the exact two-pass solver when D > kMaxWindowBlocks or
+// the ring does not fit in LDS.
 static void choose_window(AxisPlan &A, gp_prec prec)
 {
     const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
-    int K = 0;
+    int Kmin = 0;
     double bound = A.rho;
-    while (bound > tol && K < 100000) {
+    while (bound > tol && Kmin < 100000) {
         bound *= A.rho;
-        ++K;
+        ++Kmin;
     }
-    if (A.rho == 0.0) bound = 0.0;
-    const int D = (K + 1 + kBlock - 1) / kBlock;
+    A.kmin = Kmin;
+    const int D = (Kmin + 1 + kBlock - 1) / kBlock;
     int L = 1;
     while (L < (D + 1) * kBlock) L <<= 1;
     const int64_t lds = (int64_t)L * kLanes * (int64_t)elem_bytes(prec);
     const int64_t nblocks = (A.n + kBlock - 1) / kBlock;
-    if (lds <= kMaxLdsBytes) {
-        A.K = K;
+    if (D <= kMaxWindowBlocks && lds <= kMaxLdsBytes) {
+        A.K = D * kBlock - 1;
         A.D = D;
         A.L = L;
-        A.bound = bound;
+        A.bound = std::pow(A.rho, A.K + 1);
         A.npad = (nblocks + D) * kBlock;
     } else {
         A.K = -1;
@@ -141,6 +144,39 @@ static gp_status alloc(void **ptr, size_t bytes, int64_t &counter)
     }
     counter += (int64_t)bytes;
     return GP_OK;
+}
+
+// x sweep with one wavefront per line: Q = points per lane (power of two,
+// n <= 64 Q <= 64 kXMaxQ), scan steps S = smallest with Q 2^S > Kmin (full
+// scan, S = 6, when that is not below 64 lanes), and the first point from
+// which the stored table rows no longer change.
+template <typename T>
+static void x_scan_setup(AxisPlan &A, const std::vector<std::complex<long double>> &c, gp_mode mode)
+{
+    A.xq = 0;
+    int Q = 1;
+    while ((int64_t)Q * kLanes < A.n) Q <<= 1;
+    if (Q > kXMaxQ) return;
+    A.xq = Q;
+    int S = 0;
+    while (S < 6 && (int64_t)Q * (1 << S) <= A.kmin) ++S;
+    A.scan_steps = S;
+    std::vector<T> rows;
+    table_rows<T>(c, A.n + 1, A.r, mode, false, rows);
+    int64_t qc = A.n;
+    auto same = [&](int64_t a, int64_t b) {
+        for (int k = 0; k < 6; ++k)
+            if (rows[6 * (a + 1) + k] != rows[6 * (b + 1) + k]) return false;
+        return true;
+    };
+    while (qc > 0 && same(qc - 1, A.n - 1)) --qc;
+    A.q_const = qc;
+    const T *r = &rows[6 * A.n];  // row of point n-1
+    A.c_inf[0] = (double)r[0];
+    A.c_inf[1] = (double)r[1];
+    A.b_inf[0] = (double)r[2];
+    A.b_inf[1] = (double)r[3];
+    A.b_inf[2] = (double)r[4];
 }
 
 // Upload one axis's table (forward or conjugate) to the device.
@@ -292,6 +328,13 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         A.r = dt / (4.0 * dx[a] * dx[a]);
         thomas_c(A.n, A.r, mode, cs[a], A.rho);
         choose_window(A, prec);
+        if (a == 0) {
+            if (prec == GP_C128)
+                x_scan_setup<double>(A, cs[a], mode);
+            else
+                x_scan_setup<float>(A, cs[a], mode);
+            if (A.xq > 0 && A.npad < (int64_t)A.xq * kLanes) A.npad = (int64_t)A.xq * kLanes;
+        }
     }
 
     hipError_t e = hipGetDevice(&p->device);

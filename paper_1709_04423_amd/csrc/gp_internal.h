@@ -38,6 +38,7 @@ enum SweepFlags {
 constexpr int kLanes = 64;      // one wavefront = one workgroup of the sweeps
 constexpr int kBlock = 16;      // points per block of the streaming line solver
 constexpr int kMaxLdsBytes = 64 * 1024;
+constexpr int kMaxWindowBlocks = 4;  // largest compiled window depth D (K = D kBlock - 1)
 
 // Everything a sweep launch needs; passed by value as the kernel argument.
 struct SweepParams {
@@ -50,8 +51,13 @@ struct SweepParams {
     const void *tab;      // Thomas table rows p = -1 .. npad-1: c'_p, beta_p, beta_p lo (precision of psi)
     int K;                // back-substitution window
     int lmask;            // ring slots - 1 (power of two)
-    int D;                // output delay in blocks: ceil((K + 1) / kBlock)
+    int D;                // window depth in blocks (K = D kBlock - 1)
     int nblocks;          // ceil(n / kBlock)
+    // x sweep with one wavefront per line: scan steps and the constant interior row
+    int scan_steps;
+    int64_t q_const;      // rows of points q >= q_const all equal (c_inf, b_inf)
+    double c_inf[2];      // c'_q (re, im)
+    double b_inf[3];      // beta_q (re, im hi, im lo)
     // potential substep on axis 0
     double dt, g;
     double hw2[3];        // 1/2 omega_a^2 of this step
@@ -74,6 +80,11 @@ struct AxisPlan {
     int D = 0, L = 0;
     int64_t npad = 0;     // table rows after the p = -1 row
     double bound = 0.0;
+    int kmin = 0;         // smallest window meeting the precision's bound
+    int xq = 0;           // x sweep: points per lane of the one-wavefront-per-line kernel (0: not used)
+    int scan_steps = 6;   // x sweep: Hillis-Steele steps (6 = full, exact)
+    int64_t q_const = 0;  // first point from which every table row is identical
+    double c_inf[2] = {0.0, 0.0}, b_inf[3] = {0.0, 0.0, 0.0};
     std::vector<double> c;             // FP64 c'_p (interleaved complex), before rounding
     void *d_tab = nullptr;             // device table (forward)
     void *d_tab_adj = nullptr;         // device table (conjugate)
@@ -130,6 +141,9 @@ double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
 hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint, int64_t step_index,
                         const void *state, hipStream_t s);
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
+hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
+constexpr int kXWavesPerGroup = 4;  // lines per workgroup of the x scan kernel
+constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,
                              double *dg, hipStream_t s);

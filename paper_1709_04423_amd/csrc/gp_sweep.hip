@@ -14,219 +14,17 @@
 // in; the eliminated values go to a per-lane ring in LDS.  Back substitution
 // u_t = y_t - c'_t u_{t+1} runs per output block of kBlock points, starting K
 // points past the block with u = 0: the neglected term is multiplied by
-// prod |c'| <= rho^(K+1) before it reaches an output, and the host picks K so
-// that rho^(K+1) is below 2^-60 (FP64) or 2^-48 (FP32).  Rows past the end of
+// prod |c'| <= rho^(K+1) before it reaches an output.  K = D kBlock - 1 for a
+// compile-time D (1..4), the smallest with rho^(K+1) below 2^-60 (FP64) or
+// 2^-48 (FP32), so the back substitution is fully unrolled.  Rows past the end of
 // a line hold c' = 0, so the tail of every line is exact.  Each point is read
 // once and written once.  When the window does not fit in LDS, k_sweep_exact
 // runs the plain two-pass Thomas algorithm (eliminated values stored in
 // place, then read back).
 #include "gp_internal.h"
+#include "gp_sweep_common.h"
 
 namespace gp {
-
-template <typename R> struct CT;
-template <> struct CT<double> {
-    using V = double2;
-};
-template <> struct CT<float> {
-    using V = float2;
-};
-
-template <typename R> struct cp {
-    R re, im;
-};
-
-template <typename R, typename V> __device__ __forceinline__ cp<R> from_v(V v) { return {v.x, v.y}; }
-template <typename V, typename R> __device__ __forceinline__ V to_v(cp<R> c)
-{
-    V v;
-    v.x = c.re;
-    v.y = c.im;
-    return v;
-}
-
-// The solver works on the CN system divided by the off-diagonal e, which has
-// unit off-diagonals:  tridiag(1, delta_p, 1) u' = beta_p u - (u_{p-1} + u_{p+1}).
-// The Thomas factorisation of the left side, LU with L = diag(1/c'_p) + S^-,
-// U = I + diag(c'_p) S^+, needs one table value per row:
-//     y_p = (rhs_p - y_{p-1}) c'_p          (forward elimination)
-//     u'_p = y_p - c'_p u'_{p+1}             (back substitution)
-// and the c' as stored define delta_p = 1/c'_p + c'_{p-1} exactly.  The host
-// derives beta_p from those same stored values: in real time beta_p =
-// -conj(delta_p), whose imaginary part is carried as a float pair (hi + lo).
-// That keeps the Hermitian part of the map's two sides equal to working
-// precision squared, so the real-time substep stays unitary in the interior of
-// every line even when the table is rounded to FP32.  Table row r (point
-// p = r - 1) holds three values: c'_p, (Re beta_p, Im beta_p hi), (Im beta_p lo, 0).
-template <int MODE, typename R, typename V>
-__device__ __forceinline__ cp<R> cn_rhs(cp<R> um1, cp<R> u, cp<R> up1, V beta, V beta_lo)
-{
-    const R sr = um1.re + up1.re, si = um1.im + up1.im;
-    if (MODE == GP_IMAG) return {beta.x * u.re - sr, beta.x * u.im - si};
-    // The small part (a discrete Laplacian plus the lo correction) is formed
-    // first and the large i Im(beta) u term added last: added after it, the lo
-    // correction would fall below that sum's rounding and be lost every time,
-    // which biases the norm by the rounding of Im(beta) per sweep.
-    R re = beta.x * u.re - sr;
-    R im = beta.x * u.im - si;
-    re -= beta_lo.x * u.im;
-    im += beta_lo.x * u.re;
-    re -= beta.y * u.im;
-    im += beta.y * u.re;
-    return {re, im};
-}
-
-// y = (rhs - y_prev) c'
-template <int MODE, typename R, typename V>
-__device__ __forceinline__ cp<R> cn_elim(cp<R> rhs, cp<R> yprev, V c)
-{
-    const R wr = rhs.re - yprev.re, wi = rhs.im - yprev.im;
-    if (MODE == GP_IMAG) return {wr * c.x, wi * c.x};
-    return {wr * c.x - wi * c.y, wr * c.y + wi * c.x};
-}
-
-// v = y - c' v
-template <int MODE, typename R, typename V>
-__device__ __forceinline__ cp<R> cn_back(cp<R> y, V c, cp<R> v)
-{
-    if (MODE == GP_IMAG) return {y.re - c.x * v.re, y.im - c.x * v.im};
-    return {y.re - (c.x * v.re - c.y * v.im), y.im - (c.x * v.im + c.y * v.re)};
-}
-
-// Sum of np FP64 partials in a fixed order; every lane of the wavefront gets
-// the same bits (lane-strided sums, then an xor butterfly of commutative adds).
-__device__ __forceinline__ double wave_sum_partials(const double *part, int np, int lane)
-{
-    double acc = 0.0;
-    for (int i = lane; i < np; i += kLanes) acc += part[i];
-    for (int off = kLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanes);
-    return acc;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int off = kLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanes);
-    return v;
-}
-
-__device__ __forceinline__ void sincos_r(double t, double *s, double *c) { sincos(t, s, c); }
-__device__ __forceinline__ void sincos_r(float t, float *s, float *c) { sincosf(t, s, c); }
-__device__ __forceinline__ double exp_r(double t) { return exp(t); }
-__device__ __forceinline__ float exp_r(float t) { return expf(t); }
-
-// Per-line state shared by the sweep kernels.
-template <typename R> struct LineCtx {
-    int64_t base;
-    bool active;
-    double scale;   // imaginary-time renormalisation of loaded values
-    R vperp;        // potential of the line's fixed coordinates (axis 0 lines)
-    R hw0;          // 1/2 omega_x^2 of this step
-    R ysq, zsq;     // squared fixed coordinates (schedule gradient)
-};
-
-template <typename R, int FLAGS>
-__device__ __forceinline__ LineCtx<R> line_setup(const SweepParams &P, int lane)
-{
-    LineCtx<R> L;
-    const int64_t line = (int64_t)blockIdx.x * kLanes + lane;
-    L.active = line < P.nlines;
-    const int64_t l = L.active ? line : 0;
-    L.base = (l % P.m1) * P.s1 + (l / P.m1) * P.s2;
-    L.scale = 1.0;
-    if (FLAGS & F_RENORM) L.scale = 1.0 / sqrt(P.dV * wave_sum_partials(P.norm_in, P.nnorm_in, lane));
-    L.vperp = R(0);
-    L.hw0 = R(P.hw2[0]);
-    L.ysq = R(0);
-    L.zsq = R(0);
-    if (FLAGS & (F_FUSE_N | F_ADJ_N)) {
-        const double y = ((double)(l % P.ny) + P.x0[1]) * P.dx[1];
-        const double z = ((double)(l / P.ny) + P.x0[2]) * P.dx[2];
-        L.vperp = R(P.hw2[1] * y * y + P.hw2[2] * z * z);
-        L.ysq = R(y * y);
-        L.zsq = R(z * z);
-    }
-    return L;
-}
-
-// Per-line potential data of an axis-0 line given its index (transposed layout).
-template <typename R>
-__device__ __forceinline__ LineCtx<R> line_ctx_of(const SweepParams &P, int64_t line)
-{
-    LineCtx<R> L;
-    L.base = line * P.n;
-    L.active = true;
-    L.scale = 1.0;
-    const uint32_t l = (uint32_t)line, ny = (uint32_t)P.ny;
-    const double y = ((double)(l % ny) + P.x0[1]) * P.dx[1];
-    const double z = ((double)(l / ny) + P.x0[2]) * P.dx[2];
-    L.vperp = R(P.hw2[1] * y * y + P.hw2[2] * z * z);
-    L.hw0 = R(P.hw2[0]);
-    L.ysq = R(y * y);
-    L.zsq = R(z * z);
-    return L;
-}
-
-// Potential + nonlinear substep on one value at point q of an axis-0 line.
-template <typename R, int MODE, int FLAGS>
-__device__ __forceinline__ cp<R> potential_substep(cp<R> u, int64_t q, const SweepParams &P,
-                                                   const LineCtx<R> &L)
-{
-    if (FLAGS & F_RENORM) {
-        u.re = R((double)u.re * L.scale);
-        u.im = R((double)u.im * L.scale);
-    }
-    const R x = R(((double)q + P.x0[0]) * P.dx[0]);
-    const R theta = R(P.dt) * (L.vperp + L.hw0 * x * x + R(P.g) * (u.re * u.re + u.im * u.im));
-    if (MODE == GP_REAL) {
-        R s, c;
-        sincos_r(theta, &s, &c);
-        return {u.re * c + u.im * s, u.im * c - u.re * s};
-    }
-    const R f = exp_r(-theta);
-    return {u.re * f, u.im * f};
-}
-
-// Adjoint of the potential substep at point t: lam (gradient of its output)
-// -> gradient of its input; accumulates the schedule and g gradient sums.
-template <typename R, int MODE, int FLAGS, typename V>
-__device__ __forceinline__ cp<R> potential_adjoint(cp<R> lam, int64_t t, const V *state,
-                                                   int64_t addr, const SweepParams &P,
-                                                   const LineCtx<R> &L, double &acc_w,
-                                                   double &acc_g)
-{
-    const cp<R> psi = from_v<R>(state[addr]);
-    const R x = R(((double)t + P.x0[0]) * P.dx[0]);
-    const R d = psi.re * psi.re + psi.im * psi.im;
-    const R theta = R(P.dt) * (L.vperp + L.hw0 * x * x + R(P.g) * d);
-    R s, c;
-    sincos_r(theta, &s, &c);
-    const R ur = psi.re * c + psi.im * s;  // u = psi e^{-i theta}
-    const R ui = psi.im * c - psi.re * s;
-    const R w = lam.re * ui - lam.im * ur;  // Im(conj(lam) u)
-    const R k2 = R(2) * R(P.dt) * R(P.g) * w;
-    const R xs2 = P.sched_axis == 0 ? x * x : (P.sched_axis == 1 ? L.ysq : L.zsq);
-    acc_w += (double)w * (double)xs2;
-    acc_g += (double)w * (double)d;
-    return {lam.re * c - lam.im * s + k2 * psi.re, lam.re * s + lam.im * c + k2 * psi.im};
-}
-
-template <typename R, int FLAGS>
-__device__ __forceinline__ void write_partials(const SweepParams &P, int lane, double nacc,
-                                               double acc_w, double acc_g)
-{
-    if (FLAGS & F_NORM_OUT) {
-        nacc = wave_sum(nacc);
-        if (lane == 0) P.norm_out[blockIdx.x] = nacc;
-    }
-    if (FLAGS & F_ADJ_N) {
-        acc_w = wave_sum(acc_w);
-        acc_g = wave_sum(acc_g);
-        if (lane == 0) {
-            P.adj_out[2 * blockIdx.x] = acc_w;
-            P.adj_out[2 * blockIdx.x + 1] = acc_g;
-        }
-    }
-}
 
 // Access patterns of the windowed solver.
 //  kStrided: lane = line, point q of the line at base + q*stride; used for the
@@ -240,7 +38,7 @@ __device__ __forceinline__ void write_partials(const SweepParams &P, int lane, d
 enum Access { kStrided = 0, kTransposed = 1 };
 constexpr int kTilePitch = kBlock + 1;  // tile row pitch in values: conflict-free b128 access
 
-template <typename R, int MODE, int FLAGS, int ACC> struct WindowSweep {
+template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
     using V = typename CT<R>::V;
     static constexpr int B = kBlock;
     const SweepParams &P;
@@ -321,13 +119,17 @@ template <typename R, int MODE, int FLAGS, int ACC> struct WindowSweep {
             um1 = u0;
             u0 = up1;
         }
-        // back substitution of output block o = j - D
-        const int o = j - P.D;
+        // back substitution of output block o = j - DW, window K = DW*B - 1: it
+        // starts at the newest eliminated point, jB + B - 2 = ob + (DW+1)B - 2
+        const int o = j - DW;
         if (o < 0) return;
         const int64_t ob = (int64_t)o * B;
         cp<R> v = {R(0), R(0)};
-        for (int64_t t = ob + B - 1 + P.K; t >= ob + B; --t)
+#pragma unroll
+        for (int i = (DW + 1) * B - 2; i >= B; --i) {
+            const int64_t t = ob + i;
             v = cn_back<MODE, R>(from_v<R>(ring[(int)((t + 1) & lmask) * kLanes + lane]), tab[3 * (t + 1)], v);
+        }
         cp<R> out[B];
 #pragma unroll
         for (int k = B - 1; k >= 0; --k) {
@@ -387,7 +189,7 @@ template <typename R, int MODE, int FLAGS, int ACC> struct WindowSweep {
 // Streaming solver with a windowed back substitution (see the file header).
 // The block loop is unrolled by two over ping-pong buffers, so the loads of
 // block j+1 stay in flight while block j is solved.
-template <typename R, int MODE, int FLAGS, int ACC>
+template <typename R, int MODE, int FLAGS, int ACC, int DW>
 __global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
                                                          typename CT<R>::V *__restrict__ psi,
                                                          const typename CT<R>::V *__restrict__ tab,
@@ -395,8 +197,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
 {
     using V = typename CT<R>::V;
     extern __shared__ char lds_raw[];
-    WindowSweep<R, MODE, FLAGS, ACC> S(P, psi, tab, state, lds_raw);
-    const int nit = P.nblocks + P.D;
+    WindowSweep<R, MODE, FLAGS, ACC, DW> S(P, psi, tab, state, lds_raw);
+    const int nit = P.nblocks + DW;
     V a[kBlock], b[kBlock];
     S.load(a, 0);
     for (int j = 0; j < nit; j += 2) {
@@ -455,25 +257,42 @@ __global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
 
 // -------------------------------------------------------------- dispatch
 
+template <typename R, int MODE, int FLAGS, int ACC, int DW>
+static void launch_window(const AxisPlan &A, const SweepParams &P, const void *tab, hipStream_t s)
+{
+    using V = typename CT<R>::V;
+    const unsigned grid = (unsigned)((A.nlines + kLanes - 1) / kLanes);
+    const size_t lds = ((size_t)A.L * kLanes + (ACC == kTransposed ? (size_t)kLanes * kTilePitch : 0)) * sizeof(V);
+    hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, ACC, DW>), dim3(grid), dim3(kLanes), lds, s, P, (V *)P.psi,
+                       (const V *)tab, (const V *)P.state);
+}
+
+template <typename R, int MODE, int FLAGS, int ACC>
+static hipError_t launch_window_d(const AxisPlan &A, const SweepParams &P, const void *tab, hipStream_t s)
+{
+    switch (A.D) {
+    case 1: launch_window<R, MODE, FLAGS, ACC, 1>(A, P, tab, s); break;
+    case 2: launch_window<R, MODE, FLAGS, ACC, 2>(A, P, tab, s); break;
+    case 3: launch_window<R, MODE, FLAGS, ACC, 3>(A, P, tab, s); break;
+    case 4: launch_window<R, MODE, FLAGS, ACC, 4>(A, P, tab, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename R, int MODE, int FLAGS>
 static hipError_t launch_one(const AxisPlan &A, const SweepParams &P, bool exact, bool transposed, const void *tab,
                              hipStream_t s)
 {
     using V = typename CT<R>::V;
-    const unsigned grid = (unsigned)((A.nlines + kLanes - 1) / kLanes);
     if (exact) {
+        const unsigned grid = (unsigned)((A.nlines + kLanes - 1) / kLanes);
         hipLaunchKernelGGL((k_sweep_exact<R, MODE, FLAGS>), dim3(grid), dim3(kLanes), 0, s, P,
                            (V *)P.psi, (const V *)tab, (const V *)P.state);
-    } else if (transposed) {
-        const size_t lds = ((size_t)A.L * kLanes + (size_t)kLanes * kTilePitch) * sizeof(V);
-        hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, kTransposed>), dim3(grid), dim3(kLanes), lds, s, P,
-                           (V *)P.psi, (const V *)tab, (const V *)P.state);
-    } else {
-        const size_t lds = (size_t)A.L * kLanes * sizeof(V);
-        hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, kStrided>), dim3(grid), dim3(kLanes), lds, s, P,
-                           (V *)P.psi, (const V *)tab, (const V *)P.state);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    if (transposed) return launch_window_d<R, MODE, FLAGS, kTransposed>(A, P, tab, s);
+    return launch_window_d<R, MODE, FLAGS, kStrided>(A, P, tab, s);
 }
 
 template <typename R, int MODE>
@@ -503,6 +322,7 @@ static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int fl
 
 int64_t sweep_groups(const gp_plan *p, int axis)
 {
+    if (axis == 0 && p->ax[0].xq > 0) return (p->ax[0].nlines + kXWavesPerGroup - 1) / kXWavesPerGroup;
     return (p->ax[axis].nlines + kLanes - 1) / kLanes;
 }
 
@@ -547,6 +367,14 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     P.norm_out = p->d_norm + parity * p->n_norm;
     P.adj_out = p->d_adj;
     const bool exact = A.K < 0;
+    P.scan_steps = A.scan_steps;
+    P.q_const = A.q_const;
+    const double sg = adjoint ? -1.0 : 1.0;  // the conjugate map's constants
+    P.c_inf[0] = A.c_inf[0];
+    P.c_inf[1] = sg * A.c_inf[1];
+    P.b_inf[0] = A.b_inf[0];
+    P.b_inf[1] = sg * A.b_inf[1];
+    P.b_inf[2] = sg * A.b_inf[2];
     // x lines are contiguous: coalesce through the LDS tile when ring + tile fit
     const size_t tr_lds = ((size_t)A.L * kLanes + (size_t)kLanes * kTilePitch) * elem_bytes(p->prec);
     const bool tr = axis == 0 && tr_lds <= (size_t)kMaxLdsBytes;
@@ -554,6 +382,12 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     int kind = exact ? K_SWEEP_EXACT : (axis == 0 ? K_SWEEP_X : (axis == 1 ? K_SWEEP_Y : K_SWEEP_Z));
     if (flags & F_ADJ_N) kind = K_ADJ_X;
     else if (adjoint) kind = K_ADJ_YZ;
+    if (axis == 0 && A.xq > 0) {  // one wavefront per x line
+        timing_begin(p, (flags & F_ADJ_N) ? K_ADJ_X : K_SWEEP_X, s);
+        hipError_t e = launch_x_scan(p, P, flags, tab, s);
+        timing_end(p, s);
+        return e;
+    }
     timing_begin(p, kind, s);
     hipError_t e;
     if (p->prec == GP_C128)

@@ -128,9 +128,102 @@ def test_real_time_fp32_table_is_unitary_in_the_interior():
 
 
 def test_window_depth_and_exact_fallback():
+    # K = D*16 - 1 for the smallest D whose window meets the bound
     _, _, K, rho = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C128)
-    assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and rho ** K > 2.0 ** -60
-    _, _, K32, _ = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C64)
-    assert K32 < K
+    assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and (K + 1) % 16 == 0
+    assert rho ** (K + 1 - 16) > 2.0 ** -60
+    _, _, K32, rho32 = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C64)
+    assert rho32 ** (K32 + 1) <= 2.0 ** -48 and K32 <= K
+    _, _, K2, rho2 = binding.thomas_table(256, 0.05, 1e-3, binding.GP_REAL, binding.GP_C128)
+    assert K2 == 31 and rho2 ** 16 > 2.0 ** -60
     _, _, Kx, rho_x = binding.thomas_table(64, 0.05, 0.2, binding.GP_REAL, binding.GP_C128)
     assert Kx == -1 and rho_x > 0.8
+
+
+def solve_scan(c, beta, u, lanes=64, steps=None):
+    """The x kernel's algorithm: Q points per lane, per-lane affine maps,
+    Hillis-Steele scans of `steps` steps (default: full), then local apply."""
+    n = len(u)
+    Q = 1
+    while Q * lanes < n:
+        Q *= 2
+    S = 6 if steps is None else steps
+    N = Q * lanes
+    up = np.zeros(N + 2, complex)
+    up[1:n + 1] = u
+    cz = np.zeros(N, complex)
+    bz = np.zeros(N, complex)
+    cz[:n], bz[:n] = c, beta
+    rhs = bz * up[1:N + 1] - (up[0:N] + up[2:N + 2])
+    a, f = -cz, cz * rhs
+    A = np.ones(lanes, complex)
+    F = np.zeros(lanes, complex)
+    for L in range(lanes):
+        Ai, Fi = 1.0 + 0j, 0j
+        for i in range(Q):
+            p = L * Q + i
+            Fi = a[p] * Fi + f[p]
+            Ai = a[p] * Ai
+        A[L], F[L] = Ai, Fi
+    for s in range(S):
+        d = 1 << s
+        A2, F2 = A.copy(), F.copy()
+        for L in range(d, lanes):
+            F2[L] = A[L] * F[L - d] + F[L]
+            A2[L] = A[L] * A[L - d]
+        A, F = A2, F2
+    y = np.zeros(N, complex)
+    for L in range(lanes):
+        yy = F[L - 1] if L > 0 else 0
+        for i in range(Q):
+            p = L * Q + i
+            yy = a[p] * yy + f[p]
+            y[p] = yy
+    B = np.ones(lanes, complex)
+    G = np.zeros(lanes, complex)
+    for L in range(lanes):
+        Bi, Gi = 1.0 + 0j, 0j
+        for i in range(Q - 1, -1, -1):
+            p = L * Q + i
+            Gi = a[p] * Gi + y[p]
+            Bi = a[p] * Bi
+        B[L], G[L] = Bi, Gi
+    for s in range(S):
+        d = 1 << s
+        B2, G2 = B.copy(), G.copy()
+        for L in range(lanes - d):
+            G2[L] = B[L] * G[L + d] + G[L]
+            B2[L] = B[L] * B[L + d]
+        B, G = B2, G2
+    v = np.zeros(N, complex)
+    for L in range(lanes):
+        vv = G[L + 1] if L + 1 < lanes else 0
+        for i in range(Q - 1, -1, -1):
+            p = L * Q + i
+            vv = a[p] * vv + y[p]
+            v[p] = vv
+    return v[:n]
+
+
+@pytest.mark.parametrize("mode", [binding.GP_IMAG, binding.GP_REAL])
+@pytest.mark.parametrize("case", [(1, 0.05, 1e-3), (37, 0.2, 1e-2), (256, 0.05, 2e-4), (300, 0.05, 1e-3),
+                                  (512, 0.05, 5e-4), (64, 0.05, 0.2)])
+def test_x_scan_algorithm(mode, case):
+    n, dx, dt = case
+    c, beta, K, rho = binding.thomas_table(n, dx, dt, mode, binding.GP_C128)
+    A, B = cn_dense(n, dx, dt, mode)
+    u = np.random.default_rng(n + 7).standard_normal(n) + 1j * np.random.default_rng(n + 8).standard_normal(n)
+    ref = np.linalg.solve(A, B @ u)
+    assert np.max(np.abs(solve_scan(c, beta, u) - ref)) <= 1e-14 * np.max(np.abs(ref))
+    # truncated scan: the plan's step count reaches Kmin + 1 points back
+    kmin = 0
+    while rho > 0 and rho ** (kmin + 1) > 2.0 ** -60:
+        kmin += 1
+    Q = 1
+    while Q * 64 < n:
+        Q *= 2
+    S = 0
+    while S < 6 and Q * (1 << S) <= kmin:
+        S += 1
+    got = solve_scan(c, beta, u, steps=S)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
