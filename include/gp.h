@@ -84,7 +84,8 @@ typedef struct {
 typedef struct {
     int ndim;
     int64_t n[3];
-    int window[3];        /* back-substitution window K per axis; -1 = exact two-pass solve */
+    int window[3];        /* truncation window K per axis: a value K points away is neglected
+                             after decaying by rho^(K+1); -1 = exact solve */
     double rho[3];        /* max |c'_i| of the Thomas recurrence per axis */
     double window_bound[3]; /* rho^(K+1): bound on the window's relative truncation */
     int64_t step;         /* index of the next step (selects the trap schedule) */

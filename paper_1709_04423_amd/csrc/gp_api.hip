@@ -23,6 +23,18 @@ gp_status hip_fail(hipError_t e, const char *what)
     return GP_EHIP;
 }
 
+static gp_status alloc(void **ptr, size_t bytes, int64_t &counter)
+{
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EHIP;
+    }
+    counter += (int64_t)bytes;
+    return GP_OK;
+}
+
 size_t elem_bytes(gp_prec prec) { return prec == GP_C128 ? 16 : 8; }
 
 double coord0(int64_t n) { return -0.5 * (double)n; }
@@ -98,12 +110,15 @@ static void table_rows(const std::vector<std::complex<long double>> &c, int64_t 
     }
 }
 
-// Window: D = ceil((Kmin + 1) / kBlock) for the smallest Kmin with
-// rho^(Kmin+1) <= tol, used as K = D kBlock - 1 (the back substitution then
-// starts at the newest eliminated point); ring of next_pow2((D+1) kBlock)
-// slots.  K = -1 selects the exact two-pass solver when D > kMaxWindowBlocks or
-// the ring does not fit in LDS.
-static void choose_window(AxisPlan &A, gp_prec prec)
+// Window: blocks of B points (4 on the strided axes, 16 for transposed x
+// lines), D = ceil((Kmin + 1) / B) for the smallest Kmin with rho^(Kmin+1) <=
+// tol, used as K = D B - 1 (the back substitution then starts at the newest
+// eliminated point); ring of next_pow2((D+1) B) slots.  K = -1 selects the
+// exact two-pass solver when K + 1 > kMaxWindowPoints or the ring (plus the
+// transposed tile) does not fit in LDS.  Lines are split into segments until
+// about two wavefronts per SIMD are in flight, keeping every segment at least
+// four windows long.
+static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
 {
     const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
     int Kmin = 0;
@@ -113,17 +128,23 @@ static void choose_window(AxisPlan &A, gp_prec prec)
         ++Kmin;
     }
     A.kmin = Kmin;
-    const int D = (Kmin + 1 + kBlock - 1) / kBlock;
+    A.B = B;
+    const int D = (Kmin + 1 + B - 1) / B;
     int L = 1;
-    while (L < (D + 1) * kBlock) L <<= 1;
-    const int64_t lds = (int64_t)L * kLanes * (int64_t)elem_bytes(prec);
-    const int64_t nblocks = (A.n + kBlock - 1) / kBlock;
-    if (D <= kMaxWindowBlocks && lds <= kMaxLdsBytes) {
-        A.K = D * kBlock - 1;
+    while (L < (D + 1) * B) L <<= 1;
+    const int64_t eb = (int64_t)elem_bytes(prec);
+    const int64_t lds = (int64_t)L * kLanes * eb + (tile ? (int64_t)kLanes * (B + 1) * eb : 0);
+    const int64_t nblocks = (A.n + B - 1) / B;
+    A.segs = 1;
+    if (D * B <= kMaxWindowPoints && lds <= kMaxLdsBytes) {
+        A.K = D * B - 1;
         A.D = D;
         A.L = L;
         A.bound = std::pow(A.rho, A.K + 1);
-        A.npad = (nblocks + D) * kBlock;
+        A.npad = (nblocks + D) * B;
+        const int64_t waves = (A.nlines + kLanes - 1) / kLanes;
+        if (!tile)
+            while (A.segs < 8 && waves * A.segs < 2048 && nblocks / (A.segs + 1) >= 4 * (D + 1)) ++A.segs;
     } else {
         A.K = -1;
         A.D = 0;
@@ -132,18 +153,6 @@ static void choose_window(AxisPlan &A, gp_prec prec)
         A.npad = A.n + 1;
     }
     if (A.npad < A.n + 1) A.npad = A.n + 1;
-}
-
-static gp_status alloc(void **ptr, size_t bytes, int64_t &counter)
-{
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) {
-        *ptr = nullptr;
-        set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EHIP;
-    }
-    counter += (int64_t)bytes;
-    return GP_OK;
 }
 
 // x sweep with one wavefront per line: Q = points per lane (power of two,
@@ -210,6 +219,7 @@ static void free_plan(gp_plan *p)
         if (p->ax[a].d_tab) hipFree(p->ax[a].d_tab);
         if (p->ax[a].d_tab_adj) hipFree(p->ax[a].d_tab_adj);
     }
+    if (p->d_work) hipFree(p->d_work);
     if (p->d_norm) hipFree(p->d_norm);
     if (p->d_adj) hipFree(p->d_adj);
     if (p->d_obs) hipFree(p->d_obs);
@@ -218,6 +228,34 @@ static void free_plan(gp_plan *p)
 }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Buffers of the sweep along `axis`: the strided sweeps run out of place (a
+// segmented line would otherwise read points its neighbour segment has already
+// written), and the last sweep of a step writes the caller's grid.
+//   forward  3D: x psi->psi, y psi->work, z work->psi;  2D: x psi->work, y work->psi
+//   adjoint  3D: z lam->work, y work->lam, x lam->lam;  2D: y lam->work, x work->lam
+static void sweep_buffers(gp_plan *p, void *grid, int axis, bool adjoint, void **src, void **dst)
+{
+    void *w = p->d_work;
+    *src = *dst = grid;
+    if (p->ndim == 3) {
+        if (!adjoint) {
+            if (axis == 1) *dst = w;
+            if (axis == 2) *src = w;
+        } else {
+            if (axis == 2) *dst = w;
+            if (axis == 1) *src = w;
+        }
+    } else if (p->ndim == 2) {
+        if (!adjoint) {
+            if (axis == 0) *dst = w;
+            if (axis == 1) *src = w;
+        } else {
+            if (axis == 1) *dst = w;
+            if (axis == 0) *src = w;
+        }
+    }
+}
 
 }  // namespace gp
 
@@ -327,7 +365,7 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         }
         A.r = dt / (4.0 * dx[a] * dx[a]);
         thomas_c(A.n, A.r, mode, cs[a], A.rho);
-        choose_window(A, prec);
+        choose_window(A, prec, a == 0 ? kBlock : 4, a == 0);
         if (a == 0) {
             if (prec == GP_C128)
                 x_scan_setup<double>(A, cs[a], mode);
@@ -352,6 +390,7 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     p->n_norm = maxg;
     p->n_adj = maxg;
     p->n_obs_blocks = obs_groups(p);
+    if (st == GP_OK && ndim >= 2) st = alloc(&p->d_work, (size_t)npts * elem_bytes(prec), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_norm, 2 * maxg * sizeof(double), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_adj, 2 * maxg * sizeof(double), p->device_bytes);
     if (st == GP_OK)
@@ -385,6 +424,8 @@ gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info)
     for (int a = 0; a < 3; ++a) {
         info->n[a] = a < plan->ndim ? plan->n[a] : 1;
         info->window[a] = a < plan->ndim ? plan->ax[a].K : 0;
+        if (a == 0 && plan->ax[0].xq > 0)  // scan kernel: a carry reaches Q 2^S points (S = 6: whole line, exact)
+            info->window[0] = plan->ax[0].scan_steps >= 6 ? -1 : plan->ax[0].xq * (1 << plan->ax[0].scan_steps) - 1;
         info->rho[a] = a < plan->ndim ? plan->ax[a].rho : 0.0;
         info->window_bound[a] = a < plan->ndim ? plan->ax[a].bound : 0.0;
     }
@@ -404,8 +445,9 @@ gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec
     A.n = n;
     A.r = dt / (4.0 * dx * dx);
     std::vector<std::complex<long double>> cs;
+    A.nlines = 1;
     thomas_c(n, A.r, mode, cs, A.rho);
-    choose_window(A, prec);
+    choose_window(A, prec, 4, false);
     const int64_t rows = n + 1;
     auto emit = [&](auto &h) {
         for (int64_t q = 0; q < n; ++q) {
@@ -444,7 +486,9 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
             int flags = 0;
             if (a == 0) flags |= F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
             if (imag && a == p->ndim - 1) flags |= F_NORM_OUT;
-            e = launch_sweep(p, a, psi, flags, false, n, nullptr, s);
+            void *src, *dst;
+            sweep_buffers(p, psi, a, false, &src, &dst);
+            e = launch_sweep(p, a, src, dst, flags, false, n, nullptr, s);
             if (e != hipSuccess) return hip_fail(e, "sweep launch");
         }
     }
@@ -499,7 +543,9 @@ gp_status gp_step_adjoint(gp_plan *p, const void *states, void *lambda, int64_t 
         const int64_t n = n_first + k;
         const void *st = (const char *)states + (size_t)k * bytes;
         for (int a = p->ndim - 1; a >= 0; --a) {
-            e = launch_sweep(p, a, lambda, a == 0 ? F_ADJ_N : 0, true, n, st, s);
+            void *src, *dst;
+            sweep_buffers(p, lambda, a, true, &src, &dst);
+            e = launch_sweep(p, a, src, dst, a == 0 ? F_ADJ_N : 0, true, n, st, s);
             if (e != hipSuccess) return hip_fail(e, "adjoint sweep launch");
         }
         double w[3];

@@ -36,13 +36,14 @@ enum SweepFlags {
 };
 
 constexpr int kLanes = 64;      // one wavefront = one workgroup of the sweeps
-constexpr int kBlock = 16;      // points per block of the streaming line solver
+constexpr int kBlock = 16;      // points per block of the transposed x solver (strided axes use 4)
 constexpr int kMaxLdsBytes = 64 * 1024;
-constexpr int kMaxWindowBlocks = 4;  // largest compiled window depth D (K = D kBlock - 1)
+constexpr int kMaxWindowPoints = 32; // largest compiled window (K + 1 = D B points)
 
 // Everything a sweep launch needs; passed by value as the kernel argument.
 struct SweepParams {
-    void *psi;            // in/out grid
+    void *psi;            // input grid
+    void *out;            // output grid (may equal psi)
     const void *state;    // F_ADJ_N: input state of the step being reversed
     int64_t n;            // line length
     int64_t stride;       // element stride along the line
@@ -78,6 +79,8 @@ struct AxisPlan {
     double rho = 0.0;
     int K = 0;            // window; -1 = exact two-pass solver
     int D = 0, L = 0;
+    int B = 4;            // points per block of the windowed solver
+    int segs = 1;         // segments per line (windowed solver)
     int64_t npad = 0;     // table rows after the p = -1 row
     double bound = 0.0;
     int kmin = 0;         // smallest window meeting the precision's bound
@@ -115,6 +118,7 @@ struct gp_plan {
     double dV = 1.0;
     int device = 0;
     gp::AxisPlan ax[3];
+    void *d_work = nullptr;         // second grid: the strided sweeps run out of place
     double *d_norm = nullptr;       // norm partials of the last sweep
     int64_t n_norm = 0;
     double *d_adj = nullptr;        // adjoint partials (2 per workgroup)
@@ -138,8 +142,8 @@ size_t elem_bytes(gp_prec prec);
 double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
 
 // Sweep along one axis; flags per SweepFlags; adjoint selects the conjugate map.
-hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint, int64_t step_index,
-                        const void *state, hipStream_t s);
+hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
+                        int64_t step_index, const void *state, hipStream_t s);
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
 constexpr int kXWavesPerGroup = 4;  // lines per workgroup of the x scan kernel

@@ -36,13 +36,19 @@ namespace gp {
 //    lane%16) and transposed through an LDS tile to the one-line-per-lane layout
 //    of the solver; outputs go back the same way.
 enum Access { kStrided = 0, kTransposed = 1 };
-constexpr int kTilePitch = kBlock + 1;  // tile row pitch in values: conflict-free b128 access
 
-template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
+// One wavefront streaming its 64 lines (one per lane) in blocks of BB points.
+// A line may be split into segments (gridDim.y of them): segment s writes the
+// output blocks [s nb/segs, (s+1) nb/segs) and starts its forward elimination
+// DW blocks earlier from y = 0 -- after at least K + 1 recurrence steps that
+// start has decayed below the window bound, as in the back substitution.
+template <typename R, int MODE, int FLAGS, int ACC, int DW, int BB> struct WindowSweep {
     using V = typename CT<R>::V;
-    static constexpr int B = kBlock;
+    static constexpr int B = BB;
+    static constexpr int kPitch = BB + 1;  // tile row pitch in values: conflict-free b128 access
     const SweepParams &P;
-    V *__restrict__ psi;
+    const V *src;  // input grid (may equal dst: each point is read before it is written)
+    V *dst;        // output grid
     const V *__restrict__ tab;
     const V *__restrict__ state;
     V *ring;
@@ -51,11 +57,13 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
     int lane;
     int64_t n, stride, base, l0;
     int lmask;
+    int o_lo, o_hi;  // output blocks of this segment
     cp<R> um1, u0, dprev;
     double nacc, acc_w, acc_g;
 
-    __device__ __forceinline__ WindowSweep(const SweepParams &P_, V *psi_, const V *tab_, const V *state_, char *lds)
-        : P(P_), psi(psi_), tab(tab_), state(state_)
+    __device__ __forceinline__ WindowSweep(const SweepParams &P_, const V *src_, V *dst_, const V *tab_,
+                                           const V *state_, char *lds)
+        : P(P_), src(src_), dst(dst_), tab(tab_), state(state_)
     {
         lane = threadIdx.x;
         L = line_setup<R, FLAGS>(P, lane);
@@ -66,11 +74,32 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
         lmask = P.lmask;
         ring = reinterpret_cast<V *>(lds);
         tile = ring + (size_t)(lmask + 1) * kLanes;
+        const int nb = P.nblocks, segs = gridDim.y, s = blockIdx.y;
+        o_lo = (int)((int64_t)s * nb / segs);
+        o_hi = (int)((int64_t)(s + 1) * nb / segs);
         um1 = u0 = dprev = cp<R>{R(0), R(0)};
         nacc = acc_w = acc_g = 0.0;
     }
 
     __device__ __forceinline__ static V zero() { return to_v<V>(cp<R>{R(0), R(0)}); }
+
+    __device__ __forceinline__ V load_point(int64_t q) const
+    {
+        return (L.active && q >= 0 && q < n) ? src[base + q * stride] : zero();
+    }
+
+    // Values u_{q-2}, u_{q-1} before the first eliminated point of block j0.
+    __device__ __forceinline__ void start(int j0)
+    {
+        if (j0 == 0) return;  // ghosts
+        const int64_t q = (int64_t)j0 * B;
+        um1 = from_v<R>(load_point(q - 2));
+        u0 = from_v<R>(load_point(q - 1));
+        if (FLAGS & F_FUSE_N) {
+            um1 = potential_substep<R, MODE, FLAGS>(um1, q - 2, P, L);
+            u0 = potential_substep<R, MODE, FLAGS>(u0, q - 1, P, L);
+        }
+    }
 
     // Issue the loads of block j.
     __device__ __forceinline__ void load(V (&buf)[B], int j) const
@@ -78,29 +107,28 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
         const int64_t q0 = (int64_t)j * B;
         if (ACC == kStrided) {
 #pragma unroll
-            for (int k = 0; k < B; ++k) buf[k] = (L.active && q0 + k < n) ? psi[base + (q0 + k) * stride] : zero();
+            for (int k = 0; k < B; ++k) buf[k] = (L.active && q0 + k < n) ? src[base + (q0 + k) * stride] : zero();
         } else {
             const int pt = lane & (B - 1);
             const int64_t q = q0 + pt;
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const int64_t line = l0 + i * (kLanes / B) + lane / B;
-                buf[i] = (line < P.nlines && q < n) ? psi[line * n + q] : zero();
+                buf[i] = (line < P.nlines && q < n) ? src[line * n + q] : zero();
             }
         }
     }
 
-    // Solve block j (values in buf) and write output block j - D.
+    // Solve block j (values in buf) and write output block j - DW if this segment owns it.
     __device__ __forceinline__ void process(V (&buf)[B], int j)
     {
         V own[B];
         if (ACC == kTransposed) {
 #pragma unroll
-            for (int i = 0; i < B; ++i)
-                tile[(i * (kLanes / B) + lane / B) * kTilePitch + (lane & (B - 1))] = buf[i];
+            for (int i = 0; i < B; ++i) tile[(i * (kLanes / B) + lane / B) * kPitch + (lane & (B - 1))] = buf[i];
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < B; ++k) own[k] = tile[lane * kTilePitch + k];
+            for (int k = 0; k < B; ++k) own[k] = tile[lane * kPitch + k];
             __syncthreads();
         } else {
 #pragma unroll
@@ -122,7 +150,7 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
         // back substitution of output block o = j - DW, window K = DW*B - 1: it
         // starts at the newest eliminated point, jB + B - 2 = ob + (DW+1)B - 2
         const int o = j - DW;
-        if (o < 0) return;
+        if (o < o_lo || o >= o_hi) return;
         const int64_t ob = (int64_t)o * B;
         cp<R> v = {R(0), R(0)};
 #pragma unroll
@@ -147,12 +175,12 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
                     if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
                     if (FLAGS & F_ADJ_N)
                         if (L.active) w = potential_adjoint<R, MODE, FLAGS>(w, t, state, addr, P, L, acc_w, acc_g);
-                    if (L.active) psi[addr] = to_v<V>(w);
+                    if (L.active) dst[addr] = to_v<V>(w);
                 }
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < B; ++k) tile[lane * kTilePitch + k] = to_v<V>(out[k]);
+            for (int k = 0; k < B; ++k) tile[lane * kPitch + k] = to_v<V>(out[k]);
             __syncthreads();
             const int pt = lane & (B - 1);
             const int64_t t = ob + pt;
@@ -160,7 +188,7 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
             for (int i = 0; i < B; ++i) {
                 const int lo = i * (kLanes / B) + lane / B;
                 const int64_t line = l0 + lo;
-                cp<R> w = from_v<R>(tile[lo * kTilePitch + pt]);
+                cp<R> w = from_v<R>(tile[lo * kPitch + pt]);
                 if (line < P.nlines && t < n) {
                     const int64_t addr = line * n + t;
                     if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
@@ -168,7 +196,7 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
                         const LineCtx<R> Lw = line_ctx_of<R>(P, line);
                         w = potential_adjoint<R, MODE, FLAGS>(w, t, state, addr, P, Lw, acc_w, acc_g);
                     }
-                    psi[addr] = to_v<V>(w);
+                    dst[addr] = to_v<V>(w);
                 }
             }
             __syncthreads();
@@ -189,23 +217,25 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW> struct WindowSweep {
 // Streaming solver with a windowed back substitution (see the file header).
 // The block loop is unrolled by two over ping-pong buffers, so the loads of
 // block j+1 stay in flight while block j is solved.
-template <typename R, int MODE, int FLAGS, int ACC, int DW>
-__global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
-                                                         typename CT<R>::V *__restrict__ psi,
+template <typename R, int MODE, int FLAGS, int ACC, int DW, int BB>
+__global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P, const typename CT<R>::V *src,
+                                                         typename CT<R>::V *dst,
                                                          const typename CT<R>::V *__restrict__ tab,
                                                          const typename CT<R>::V *__restrict__ state)
 {
     using V = typename CT<R>::V;
     extern __shared__ char lds_raw[];
-    WindowSweep<R, MODE, FLAGS, ACC, DW> S(P, psi, tab, state, lds_raw);
-    const int nit = P.nblocks + DW;
-    V a[kBlock], b[kBlock];
-    S.load(a, 0);
-    for (int j = 0; j < nit; j += 2) {
-        if (j + 1 < nit) S.load(b, j + 1);
+    WindowSweep<R, MODE, FLAGS, ACC, DW, BB> S(P, src, dst, tab, state, lds_raw);
+    const int j0 = S.o_lo - DW > 0 ? S.o_lo - DW : 0;
+    const int j1 = S.o_hi + DW;  // exclusive: the last output block o_hi-1 is written at j = o_hi-1+DW
+    S.start(j0);
+    V a[BB], b[BB];
+    S.load(a, j0);
+    for (int j = j0; j < j1; j += 2) {
+        if (j + 1 < j1) S.load(b, j + 1);
         S.process(a, j);
-        if (j + 1 >= nit) break;
-        if (j + 2 < nit) S.load(a, j + 2);
+        if (j + 1 >= j1) break;
+        if (j + 2 < j1) S.load(a, j + 2);
         S.process(b, j + 1);
     }
     S.finish();
@@ -214,8 +244,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_window(SweepParams P,
 // Plain two-pass Thomas algorithm: forward elimination stores d in place,
 // back substitution reads it back.  Exact for any window; twice the traffic.
 template <typename R, int MODE, int FLAGS>
-__global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
-                                                        typename CT<R>::V *__restrict__ psi,
+__global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P, const typename CT<R>::V *src,
+                                                        typename CT<R>::V *dst,
                                                         const typename CT<R>::V *__restrict__ tab,
                                                         const typename CT<R>::V *__restrict__ state)
 {
@@ -227,17 +257,17 @@ __global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
 
     if (L.active) {
         cp<R> um1 = {R(0), R(0)}, dprev = {R(0), R(0)};
-        cp<R> u0 = from_v<R>(psi[base]);
+        cp<R> u0 = from_v<R>(src[base]);
         if (FLAGS & F_FUSE_N) u0 = potential_substep<R, MODE, FLAGS>(u0, 0, P, L);
         for (int64_t q = 1; q <= n; ++q) {
             cp<R> up1 = {R(0), R(0)};
             if (q < n) {
-                up1 = from_v<R>(psi[base + q * stride]);
+                up1 = from_v<R>(src[base + q * stride]);
                 if (FLAGS & F_FUSE_N) up1 = potential_substep<R, MODE, FLAGS>(up1, q, P, L);
             }
             const cp<R> d = cn_elim<MODE, R>(cn_rhs<MODE, R>(um1, u0, up1, tab[3 * q + 1], tab[3 * q + 2]), dprev,
                                              tab[3 * q]);
-            psi[base + (q - 1) * stride] = to_v<V>(d);
+            dst[base + (q - 1) * stride] = to_v<V>(d);
             dprev = d;
             um1 = u0;
             u0 = up1;
@@ -245,11 +275,11 @@ __global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
         cp<R> v = {R(0), R(0)};
         for (int64_t t = n - 1; t >= 0; --t) {
             const int64_t addr = base + t * stride;
-            v = cn_back<MODE, R>(from_v<R>(psi[addr]), tab[3 * (t + 1)], v);
+            v = cn_back<MODE, R>(from_v<R>(dst[addr]), tab[3 * (t + 1)], v);
             cp<R> w = v;
             if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
             if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, t, state, addr, P, L, acc_w, acc_g);
-            psi[addr] = to_v<V>(w);
+            dst[addr] = to_v<V>(w);
         }
     }
     write_partials<R, FLAGS>(P, lane, nacc, acc_w, acc_g);
@@ -257,25 +287,41 @@ __global__ __launch_bounds__(kLanes) void k_sweep_exact(SweepParams P,
 
 // -------------------------------------------------------------- dispatch
 
-template <typename R, int MODE, int FLAGS, int ACC, int DW>
+template <typename R, int MODE, int FLAGS, int ACC, int DW, int BB>
 static void launch_window(const AxisPlan &A, const SweepParams &P, const void *tab, hipStream_t s)
 {
     using V = typename CT<R>::V;
-    const unsigned grid = (unsigned)((A.nlines + kLanes - 1) / kLanes);
-    const size_t lds = ((size_t)A.L * kLanes + (ACC == kTransposed ? (size_t)kLanes * kTilePitch : 0)) * sizeof(V);
-    hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, ACC, DW>), dim3(grid), dim3(kLanes), lds, s, P, (V *)P.psi,
-                       (const V *)tab, (const V *)P.state);
+    const dim3 grid((unsigned)((A.nlines + kLanes - 1) / kLanes), (unsigned)A.segs);
+    const size_t lds = ((size_t)A.L * kLanes + (ACC == kTransposed ? (size_t)kLanes * (BB + 1) : 0)) * sizeof(V);
+    hipLaunchKernelGGL((k_sweep_window<R, MODE, FLAGS, ACC, DW, BB>), grid, dim3(kLanes), lds, s, P,
+                       (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
 }
 
 template <typename R, int MODE, int FLAGS, int ACC>
 static hipError_t launch_window_d(const AxisPlan &A, const SweepParams &P, const void *tab, hipStream_t s)
 {
-    switch (A.D) {
-    case 1: launch_window<R, MODE, FLAGS, ACC, 1>(A, P, tab, s); break;
-    case 2: launch_window<R, MODE, FLAGS, ACC, 2>(A, P, tab, s); break;
-    case 3: launch_window<R, MODE, FLAGS, ACC, 3>(A, P, tab, s); break;
-    case 4: launch_window<R, MODE, FLAGS, ACC, 4>(A, P, tab, s); break;
-    default: return hipErrorInvalidValue;
+    if (ACC == kTransposed) {  // blocks of 16 points
+        if (A.B != 16) return hipErrorInvalidValue;
+        switch (A.D) {
+        case 1: launch_window<R, MODE, FLAGS, ACC, 1, 16>(A, P, tab, s); break;
+        case 2: launch_window<R, MODE, FLAGS, ACC, 2, 16>(A, P, tab, s); break;
+        case 3: launch_window<R, MODE, FLAGS, ACC, 3, 16>(A, P, tab, s); break;
+        case 4: launch_window<R, MODE, FLAGS, ACC, 4, 16>(A, P, tab, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {  // blocks of 4 points
+        if (A.B != 4) return hipErrorInvalidValue;
+        switch (A.D) {
+        case 1: launch_window<R, MODE, FLAGS, ACC, 1, 4>(A, P, tab, s); break;
+        case 2: launch_window<R, MODE, FLAGS, ACC, 2, 4>(A, P, tab, s); break;
+        case 3: launch_window<R, MODE, FLAGS, ACC, 3, 4>(A, P, tab, s); break;
+        case 4: launch_window<R, MODE, FLAGS, ACC, 4, 4>(A, P, tab, s); break;
+        case 5: launch_window<R, MODE, FLAGS, ACC, 5, 4>(A, P, tab, s); break;
+        case 6: launch_window<R, MODE, FLAGS, ACC, 6, 4>(A, P, tab, s); break;
+        case 7: launch_window<R, MODE, FLAGS, ACC, 7, 4>(A, P, tab, s); break;
+        case 8: launch_window<R, MODE, FLAGS, ACC, 8, 4>(A, P, tab, s); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
@@ -288,7 +334,7 @@ static hipError_t launch_one(const AxisPlan &A, const SweepParams &P, bool exact
     if (exact) {
         const unsigned grid = (unsigned)((A.nlines + kLanes - 1) / kLanes);
         hipLaunchKernelGGL((k_sweep_exact<R, MODE, FLAGS>), dim3(grid), dim3(kLanes), 0, s, P,
-                           (V *)P.psi, (const V *)tab, (const V *)P.state);
+                           (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
         return hipGetLastError();
     }
     if (transposed) return launch_window_d<R, MODE, FLAGS, kTransposed>(A, P, tab, s);
@@ -322,8 +368,10 @@ static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int fl
 
 int64_t sweep_groups(const gp_plan *p, int axis)
 {
-    if (axis == 0 && p->ax[0].xq > 0) return (p->ax[0].nlines + kXWavesPerGroup - 1) / kXWavesPerGroup;
-    return (p->ax[axis].nlines + kLanes - 1) / kLanes;
+    const AxisPlan &A = p->ax[axis];
+    if (axis == 0 && A.xq > 0) return (A.nlines + kXWavesPerGroup - 1) / kXWavesPerGroup;
+    const int64_t g = (A.nlines + kLanes - 1) / kLanes;
+    return A.K < 0 ? g : g * A.segs;
 }
 
 void omega_at_step(const gp_plan *p, int64_t step, double w[3])
@@ -332,12 +380,13 @@ void omega_at_step(const gp_plan *p, int64_t step, double w[3])
     if (!p->sched.empty() && step >= 0 && step < (int64_t)p->sched.size()) w[p->sched_axis] = p->sched[step];
 }
 
-hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint, int64_t step_index,
-                        const void *state, hipStream_t s)
+hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
+                        int64_t step_index, const void *state, hipStream_t s)
 {
     const AxisPlan &A = p->ax[axis];
     SweepParams P{};
-    P.psi = psi;
+    P.psi = const_cast<void *>(src);
+    P.out = dst;
     P.state = state;
     P.n = A.n;
     P.stride = A.stride;
@@ -348,7 +397,7 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     P.K = A.K < 0 ? 0 : A.K;
     P.lmask = A.L > 0 ? A.L - 1 : 0;
     P.D = A.D;
-    P.nblocks = (int)((A.n + kBlock - 1) / kBlock);
+    P.nblocks = A.B > 0 ? (int)((A.n + A.B - 1) / A.B) : 0;
     P.dt = p->dt;
     P.g = p->g;
     double w[3];
@@ -376,8 +425,7 @@ hipError_t launch_sweep(gp_plan *p, int axis, void *psi, int flags, bool adjoint
     P.b_inf[1] = sg * A.b_inf[1];
     P.b_inf[2] = sg * A.b_inf[2];
     // x lines are contiguous: coalesce through the LDS tile when ring + tile fit
-    const size_t tr_lds = ((size_t)A.L * kLanes + (size_t)kLanes * kTilePitch) * elem_bytes(p->prec);
-    const bool tr = axis == 0 && tr_lds <= (size_t)kMaxLdsBytes;
+    const bool tr = axis == 0;  // x lines too long for the scan kernel: coalesced through an LDS tile
     const void *tab = adjoint ? A.d_tab_adj : A.d_tab;
     int kind = exact ? K_SWEEP_EXACT : (axis == 0 ? K_SWEEP_X : (axis == 1 ? K_SWEEP_Y : K_SWEEP_Z));
     if (flags & F_ADJ_N) kind = K_ADJ_X;

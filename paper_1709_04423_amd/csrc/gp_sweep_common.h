@@ -246,16 +246,17 @@ template <typename R, int FLAGS>
 __device__ __forceinline__ void write_partials(const SweepParams &P, int lane, double nacc,
                                                double acc_w, double acc_g)
 {
+    const int64_t g = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;  // one partial per workgroup and segment
     if (FLAGS & F_NORM_OUT) {
         nacc = wave_sum(nacc);
-        if (lane == 0) P.norm_out[blockIdx.x] = nacc;
+        if (lane == 0) P.norm_out[g] = nacc;
     }
     if (FLAGS & F_ADJ_N) {
         acc_w = wave_sum(acc_w);
         acc_g = wave_sum(acc_g);
         if (lane == 0) {
-            P.adj_out[2 * blockIdx.x] = acc_w;
-            P.adj_out[2 * blockIdx.x + 1] = acc_g;
+            P.adj_out[2 * g] = acc_w;
+            P.adj_out[2 * g + 1] = acc_g;
         }
     }
 }

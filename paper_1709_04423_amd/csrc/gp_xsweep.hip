@@ -63,8 +63,8 @@ __device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict
 }
 
 template <typename R, int MODE, int FLAGS, int Q>
-__global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
-                                                                   typename CT<R>::V *__restrict__ psi,
+__global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P, const typename CT<R>::V *src,
+                                                                   typename CT<R>::V *dst,
                                                                    const typename CT<R>::V *__restrict__ tab,
                                                                    const typename CT<R>::V *__restrict__ state)
 {
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int64_t q = q0 + i;
-        u[i] = (active && q < n) ? from_v<R>(psi[base + q]) : cp<R>{R(0), R(0)};
+        u[i] = (active && q < n) ? from_v<R>(src[base + q]) : cp<R>{R(0), R(0)};
         if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
     }
     // neighbours across lane boundaries (zero ghosts at the line ends)
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
             cp<R> w = u[i];
             if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
             if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, q, state, base + q, P, L, acc_w, acc_g);
-            psi[base + q] = to_v<V>(w);
+            dst[base + q] = to_v<V>(w);
         }
     }
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
@@ -198,7 +198,7 @@ static void launch_q(const SweepParams &P, const void *tab, hipStream_t s)
     using V = typename CT<R>::V;
     const unsigned grid = (unsigned)((P.nlines + kXWaves - 1) / kXWaves);
     hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
-                       (V *)P.psi, (const V *)tab, (const V *)P.state);
+                       (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
 }
 
 template <typename R, int MODE, int FLAGS>

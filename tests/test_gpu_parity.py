@@ -70,6 +70,10 @@ CASES_FP64 = [
     ((37, 29, 23), (0.2, 0.25, 0.3), 1e-3, (1.0, 2.0, 3.0), 50.0, 2),
     ((64, 48, 40), (0.2, 0.2, 0.25), 5e-4, (1.0, 1.0, 4.0), 100.0, 3),
     ((17, 1, 5), (0.3, 0.3, 0.3), 1e-2, (1.0, 1.0, 1.0), 3.0, 2),
+    # long ragged strided lines: split into several segments per line
+    ((40, 301, 20), (0.2, 0.04, 0.3), 2e-4, (1.0, 1.0, 2.0), 20.0, 2),
+    ((50, 701), (0.2, 0.03), 2e-4, (1.0, 1.0), 20.0, 3),
+    ((24, 20, 517), (0.3, 0.3, 0.025), 1e-4, (1.0, 1.0, 1.0), 20.0, 2),
 ]
 
 
@@ -99,7 +103,8 @@ def test_window_and_exact_paths_agree_on_medium_window(gp):
     plan, _, got, ref = run_case(gp, n, dx, dt, 1, omega, g, 2)
     w = plan.info()["window"]
     say(f"  windows {w}")
-    assert all(k >= 16 for k in w)
+    assert all(k >= 16 for k in w[1:])  # strided axes: windowed solver with a deep window
+    assert w[0] >= 16 or w[0] == -1     # x: scan kernel reaching as far (or the whole line)
     assert max_rel(got, ref) <= FP64_TOL
 
 

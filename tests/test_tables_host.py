@@ -7,7 +7,7 @@ import pytest
 
 from paper_1709_04423_amd import binding
 
-BLOCK = 16  # points per block of the streaming solver (kBlock in the kernels)
+BLOCK = 4  # points per block of the strided-axis solver (16 for transposed x lines)
 
 
 def cn_dense(n, dx, dt, mode, adjoint=False):
@@ -38,40 +38,46 @@ def solve_with_table(c, beta, u):
     return v
 
 
-def solve_windowed(c, beta, u, K):
-    """The kernels' streaming algorithm: blocks of BLOCK points, exact forward
-    elimination, back substitution per output block started K points past it
-    with zero, rows past the line zero."""
+def solve_windowed(c, beta, u, K, block=BLOCK, segs=1):
+    """The kernels' streaming algorithm: blocks of `block` points, forward
+    elimination as values arrive, back substitution per output block started K
+    points past it with zero, rows past the line zero; optionally the line is
+    split into `segs` segments, each starting its elimination D blocks before
+    its first output block from y = 0."""
     n = len(u)
-    D = (K + 1 + BLOCK - 1) // BLOCK
-    nblocks = (n + BLOCK - 1) // BLOCK
-    nit = nblocks + D
-    rows = nit * BLOCK + 1
+    D = (K + 1 + block - 1) // block
+    nblocks = (n + block - 1) // block
+    rows = (nblocks + D) * block + 1
     ctab = np.zeros(rows, complex)
     btab = np.zeros(rows, complex)
     ctab[1:n + 1] = c
     btab[1:n + 1] = beta
-    ext = np.zeros(nit * BLOCK + 2, complex)
+    ext = np.zeros((nblocks + D) * block + 2, complex)
     ext[:n] = u
-    y = {}
     out = np.zeros(n, complex)
-    um1 = u0 = yprev = 0
-    for j in range(nit):
-        for k in range(BLOCK):
-            q = j * BLOCK + k
-            up1 = ext[q]
-            rhs = btab[q] * u0 - (um1 + up1)
-            d = (rhs - yprev) * ctab[q]
-            y[q - 1] = d
-            yprev, um1, u0 = d, u0, up1
-        o = j - D
-        if o >= 0:
-            ob = o * BLOCK
-            v = 0
-            for t in range(ob + BLOCK - 1 + K, ob - 1, -1):
-                v = y[t] - ctab[t + 1] * v
-                if t < ob + BLOCK and t < n:
-                    out[t] = v
+    for s in range(segs):
+        o_lo, o_hi = s * nblocks // segs, (s + 1) * nblocks // segs
+        j0 = max(0, o_lo - D)
+        y = {}
+        um1 = u0 = yprev = 0
+        if j0 > 0:
+            um1, u0 = ext[j0 * block - 2], ext[j0 * block - 1]
+        for j in range(j0, o_hi + D):
+            for k in range(block):
+                q = j * block + k
+                up1 = ext[q]
+                rhs = btab[q] * u0 - (um1 + up1)
+                d = (rhs - yprev) * ctab[q]
+                y[q - 1] = d
+                yprev, um1, u0 = d, u0, up1
+            o = j - D
+            if o_lo <= o < o_hi:
+                ob = o * block
+                v = 0
+                for t in range(ob + (D + 1) * block - 2, ob - 1, -1):
+                    v = y[t] - ctab[t + 1] * v
+                    if t < ob + block and t < n:
+                        out[t] = v
     return out
 
 
@@ -93,8 +99,9 @@ def test_table_factorises_cn_fp64(mode, adjoint, case):
     got = solve_with_table(c, beta, u)
     assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
     assert K >= 0
-    win = solve_windowed(c, beta, u, K)
-    assert np.max(np.abs(win - ref)) <= 1e-14 * np.max(np.abs(ref))
+    for block, segs in ((4, 1), (4, 3), (16, 1)):
+        win = solve_windowed(c, beta, u, K, block, segs)
+        assert np.max(np.abs(win - ref)) <= 1e-14 * np.max(np.abs(ref)), (block, segs)
 
 
 @pytest.mark.parametrize("mode", [binding.GP_IMAG, binding.GP_REAL])
@@ -128,14 +135,14 @@ def test_real_time_fp32_table_is_unitary_in_the_interior():
 
 
 def test_window_depth_and_exact_fallback():
-    # K = D*16 - 1 for the smallest D whose window meets the bound
+    # K = D*4 - 1 for the smallest D whose window meets the bound
     _, _, K, rho = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C128)
-    assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and (K + 1) % 16 == 0
-    assert rho ** (K + 1 - 16) > 2.0 ** -60
+    assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and (K + 1) % 4 == 0
+    assert rho ** (K + 1 - 4) > 2.0 ** -60
     _, _, K32, rho32 = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C64)
     assert rho32 ** (K32 + 1) <= 2.0 ** -48 and K32 <= K
     _, _, K2, rho2 = binding.thomas_table(256, 0.05, 1e-3, binding.GP_REAL, binding.GP_C128)
-    assert K2 == 31 and rho2 ** 16 > 2.0 ** -60
+    assert K2 == 19 and rho2 ** 16 > 2.0 ** -60
     _, _, Kx, rho_x = binding.thomas_table(64, 0.05, 0.2, binding.GP_REAL, binding.GP_C128)
     assert Kx == -1 and rho_x > 0.8
 
