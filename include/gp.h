@@ -192,7 +192,7 @@ gp_status gp_plan_timing_enable(gp_plan *plan, int64_t capacity);
 /* Synchronise the events and report, per kernel kind (names in
  * gp_kernel_name(kind), kind = 0..GP_NUM_KERNEL_KINDS-1), the number of
  * recorded launches and their total duration in milliseconds; clears the log. */
-#define GP_NUM_KERNEL_KINDS 12
+#define GP_NUM_KERNEL_KINDS 13
 gp_status gp_plan_timing_read(gp_plan *plan, int64_t *counts, double *total_ms);
 const char *gp_kernel_name(int kind);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgp.so")
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED, GP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GP_IMAG, GP_REAL = 0, 1
 GP_C128, GP_C64 = 0, 1
-GP_NUM_KERNEL_KINDS = 12
+GP_NUM_KERNEL_KINDS = 13
 
 c_i64p = ctypes.POINTER(ctypes.c_int64)
 c_dp = ctypes.POINTER(ctypes.c_double)

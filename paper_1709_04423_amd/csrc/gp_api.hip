@@ -116,8 +116,8 @@ static void table_rows(const std::vector<std::complex<long double>> &c, int64_t 
 // eliminated point); ring of next_pow2((D+1) B) slots.  K = -1 selects the
 // exact two-pass solver when K + 1 > kMaxWindowPoints or the ring (plus the
 // transposed tile) does not fit in LDS.  Lines are split into segments until
-// about two wavefronts per SIMD are in flight, keeping every segment at least
-// four windows long.
+// about two (complex128) or four (complex64) wavefronts per SIMD are in
+// flight, keeping every segment at least four windows long.
 static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
 {
     const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
@@ -143,8 +143,10 @@ static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
         A.bound = std::pow(A.rho, A.K + 1);
         A.npad = (nblocks + D) * B;
         const int64_t waves = (A.nlines + kLanes - 1) / kLanes;
+        // about 2 wavefronts per SIMD for complex128 rows, 4 for complex64 (same bytes in flight)
+        const int64_t target = prec == GP_C128 ? 2048 : 4096;
         if (!tile)
-            while (A.segs < 8 && waves * A.segs < 2048 && nblocks / (A.segs + 1) >= 4 * (D + 1)) ++A.segs;
+            while (A.segs < 8 && waves * A.segs < target && nblocks / (A.segs + 1) >= 4 * (D + 1)) ++A.segs;
     } else {
         A.K = -1;
         A.D = 0;
@@ -188,6 +190,58 @@ static void x_scan_setup(AxisPlan &A, const std::vector<std::complex<long double
     A.b_inf[2] = (double)r[4];
 }
 
+// Multipliers of the x scan kernel's composed affine maps, per lane and scan
+// step, exactly as the kernel would compute them: lane L holds points
+// L Q .. L Q + Q - 1 with a_p = -c'_p (zero past the line); its forward map
+// multiplier is prod a_p over its points, and scan step s (d = 2^s) multiplies
+// lane L's by lane L-d's (forward) or L+d's (backward) when that lane exists.
+// Rows 0..5: forward multiplier before step s; rows 6..11: backward.
+template <typename T>
+static std::vector<T> x_scan_multipliers(const std::vector<std::complex<long double>> &c, int Q, bool conj)
+{
+    using cl = std::complex<long double>;
+    const int64_t n = (int64_t)c.size();
+    std::vector<cl> f(kLanes, cl(1.0L, 0.0L)), b(kLanes, cl(1.0L, 0.0L));
+    for (int L = 0; L < kLanes; ++L)
+        for (int i = 0; i < Q; ++i) {
+            const int64_t p = (int64_t)L * Q + i;
+            const T cr = p < n ? (T)c[p].real() : T(0), ci = p < n ? (T)c[p].imag() : T(0);
+            const cl a(-(long double)cr, -(long double)ci * (conj ? -1.0L : 1.0L));
+            f[L] *= a;
+            b[L] *= a;
+        }
+    std::vector<T> out(2 * 12 * kLanes, T(0));
+    for (int s = 0; s < 6; ++s) {
+        for (int L = 0; L < kLanes; ++L) {
+            out[2 * (s * kLanes + L)] = (T)f[L].real();
+            out[2 * (s * kLanes + L) + 1] = (T)f[L].imag();
+            out[2 * ((6 + s) * kLanes + L)] = (T)b[L].real();
+            out[2 * ((6 + s) * kLanes + L) + 1] = (T)b[L].imag();
+        }
+        const int d = 1 << s;
+        std::vector<cl> f2 = f, b2 = b;
+        for (int L = 0; L < kLanes; ++L) {
+            if (L >= d) f2[L] = f[L] * f[L - d];
+            if (L + d < kLanes) b2[L] = b[L] * b[L + d];
+        }
+        f = f2;
+        b = b2;
+    }
+    return out;
+}
+
+template <typename T>
+static gp_status upload_x_multipliers(gp_plan *p, AxisPlan &A, const std::vector<std::complex<long double>> &c,
+                                      bool conj, void **dst)
+{
+    std::vector<T> h = x_scan_multipliers<T>(c, A.xq, conj);
+    gp_status st = alloc(dst, h.size() * sizeof(T), p->device_bytes);
+    if (st != GP_OK) return st;
+    hipError_t e = hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(x multipliers)");
+    return GP_OK;
+}
+
 // Upload one axis's table (forward or conjugate) to the device.
 static gp_status upload_table(gp_plan *p, AxisPlan &A, const std::vector<std::complex<long double>> &c, bool conj,
                               void **dst)
@@ -218,6 +272,8 @@ static void free_plan(gp_plan *p)
     for (int a = 0; a < 3; ++a) {
         if (p->ax[a].d_tab) hipFree(p->ax[a].d_tab);
         if (p->ax[a].d_tab_adj) hipFree(p->ax[a].d_tab_adj);
+        if (p->ax[a].d_xmul) hipFree(p->ax[a].d_xmul);
+        if (p->ax[a].d_xmul_adj) hipFree(p->ax[a].d_xmul_adj);
     }
     if (p->d_work) hipFree(p->d_work);
     if (p->d_norm) hipFree(p->d_norm);
@@ -283,7 +339,7 @@ const char *gp_kernel_name(int kind)
 {
     static const char *names[GP_NUM_KERNEL_KINDS] = {
         "sweep_x", "sweep_y", "sweep_z", "sweep_exact", "scale", "observables",
-        "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy"};
+        "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy", "norm_final"};
     if (kind < 0 || kind >= GP_NUM_KERNEL_KINDS) return "unknown";
     return names[kind];
 }
@@ -365,6 +421,7 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         }
         A.r = dt / (4.0 * dx[a] * dx[a]);
         thomas_c(A.n, A.r, mode, cs[a], A.rho);
+        // strided axes stream blocks of 4 rows per wavefront
         choose_window(A, prec, a == 0 ? kBlock : 4, a == 0);
         if (a == 0) {
             if (prec == GP_C128)
@@ -384,6 +441,13 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     for (int a = 0; a < ndim && st == GP_OK; ++a) {
         st = upload_table(p, p->ax[a], cs[a], false, &p->ax[a].d_tab);
         if (st == GP_OK && mode == GP_REAL) st = upload_table(p, p->ax[a], cs[a], true, &p->ax[a].d_tab_adj);
+        if (st == GP_OK && a == 0 && p->ax[0].xq > 0) {
+            for (int cj = 0; cj < (mode == GP_REAL ? 2 : 1) && st == GP_OK; ++cj) {
+                void **dst = cj ? &p->ax[0].d_xmul_adj : &p->ax[0].d_xmul;
+                st = prec == GP_C128 ? upload_x_multipliers<double>(p, p->ax[0], cs[0], cj != 0, dst)
+                                     : upload_x_multipliers<float>(p, p->ax[0], cs[0], cj != 0, dst);
+            }
+        }
     }
     int64_t maxg = 1;
     for (int a = 0; a < ndim; ++a) maxg = std::max(maxg, sweep_groups(p, a));
@@ -391,7 +455,7 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     p->n_adj = maxg;
     p->n_obs_blocks = obs_groups(p);
     if (st == GP_OK && ndim >= 2) st = alloc(&p->d_work, (size_t)npts * elem_bytes(prec), p->device_bytes);
-    if (st == GP_OK) st = alloc((void **)&p->d_norm, 2 * maxg * sizeof(double), p->device_bytes);
+    if (st == GP_OK) st = alloc((void **)&p->d_norm, (2 * maxg + 2) * sizeof(double), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_adj, 2 * maxg * sizeof(double), p->device_bytes);
     if (st == GP_OK)
         st = alloc((void **)&p->d_obs, (p->n_obs_blocks + 1) * kObsFields * sizeof(double), p->device_bytes);
@@ -490,6 +554,10 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
             sweep_buffers(p, psi, a, false, &src, &dst);
             e = launch_sweep(p, a, src, dst, flags, false, n, nullptr, s);
             if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        }
+        if (imag) {
+            e = launch_norm_final(p, n, s);
+            if (e != hipSuccess) return hip_fail(e, "norm launch");
         }
     }
     p->step += nsteps;

@@ -25,6 +25,7 @@ enum KernelKind {
     K_ADJ_REDUCE = 9,
     K_BATCH = 10,
     K_COPY = 11,
+    K_NORM_FINAL = 12,
 };
 
 // Flags of the line-sweep kernel.
@@ -59,6 +60,7 @@ struct SweepParams {
     int64_t q_const;      // rows of points q >= q_const all equal (c_inf, b_inf)
     double c_inf[2];      // c'_q (re, im)
     double b_inf[3];      // beta_q (re, im hi, im lo)
+    const void *xmul;     // x scan multipliers: 12 rows x 64 lanes (forward steps 0..5, backward 0..5)
     // potential substep on axis 0
     double dt, g;
     double hw2[3];        // 1/2 omega_a^2 of this step
@@ -66,8 +68,7 @@ struct SweepParams {
     int64_t ny;           // axis-0 line index l -> (j, k) = (l % ny, l / ny)
     int sched_axis;       // F_ADJ_N: axis whose x^2 weights the schedule gradient
     // imaginary-time renormalisation
-    const double *norm_in;
-    int nnorm_in;
+    const double *norm_total;  // F_RENORM: dV-less sum |psi|^2 of the previous step (one value)
     double dV;
     double *norm_out;     // F_NORM_OUT partials, one per workgroup
     double *adj_out;      // F_ADJ_N partials, two per workgroup
@@ -91,6 +92,8 @@ struct AxisPlan {
     std::vector<double> c;             // FP64 c'_p (interleaved complex), before rounding
     void *d_tab = nullptr;             // device table (forward)
     void *d_tab_adj = nullptr;         // device table (conjugate)
+    void *d_xmul = nullptr;            // x scan multipliers (forward map)
+    void *d_xmul_adj = nullptr;        // x scan multipliers (conjugate map)
 };
 
 struct Timing {
@@ -145,8 +148,13 @@ double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
 hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
                         int64_t step_index, const void *state, hipStream_t s);
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
+hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
+// norm totals: one value per step parity, after the 2 x n_norm partials
+inline double *norm_partials(gp_plan *p, int64_t step) { return p->d_norm + (step & 1) * p->n_norm; }
+inline double *norm_total(gp_plan *p, int64_t step) { return p->d_norm + 2 * p->n_norm + (step & 1); }
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
-constexpr int kXWavesPerGroup = 4;  // lines per workgroup of the x scan kernel
+constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
+constexpr int kXLinesPerGroup = 16; // lines per workgroup of the x scan kernel (4 per wavefront)
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,

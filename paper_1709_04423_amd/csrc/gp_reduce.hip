@@ -22,26 +22,36 @@ __device__ __forceinline__ double wsum(double v)
     return v;
 }
 
-// Same fixed-order sum of FP64 partials as the sweep kernels use.
-__device__ __forceinline__ double wsum_partials(const double *part, int np, int lane)
-{
-    double acc = 0.0;
-    for (int i = lane; i < np; i += kLanes) acc += part[i];
-    return wsum(acc);
-}
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_scale(typename VT<R>::V *__restrict__ psi, int64_t npts,
-                                               const double *__restrict__ part, int np, double dV)
+                                               const double *__restrict__ total, double dV)
 {
-    const int lane = threadIdx.x & (kLanes - 1);
-    const double s = 1.0 / sqrt(dV * wsum_partials(part, np, lane));
+    const double s = 1.0 / sqrt(dV * total[0]);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts;
          i += (int64_t)gridDim.x * blockDim.x) {
         typename VT<R>::V v = psi[i];
         v.x = R((double)v.x * s);
         v.y = R((double)v.y * s);
         psi[i] = v;
+    }
+}
+
+// Sum of the per-workgroup norm partials of one step in a fixed order.
+__global__ __launch_bounds__(256) void k_norm_final(const double *__restrict__ part, int64_t np,
+                                                    double *__restrict__ total)
+{
+    __shared__ double lds[256 / kLanes];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+    acc = wsum(acc);
+    const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+    if (lane == 0) lds[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 256 / kLanes; ++w) s += lds[w];
+        total[0] = s;
     }
 }
 
@@ -177,18 +187,25 @@ int64_t obs_groups(const gp_plan *p)
 
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s)
 {
-    const int64_t last = (p->step - 1) & 1;  // buffer written by the last step's final sweep
-    const double *part = p->d_norm + last * p->n_norm;
-    const int np = (int)sweep_groups(p, p->ndim - 1);
+    const double *total = norm_total(p, p->step - 1);  // written after the last step's final sweep
     int64_t grid = (p->npts + 255) / 256;
     if (grid > 4096) grid = 4096;
     timing_begin(p, K_SCALE, s);
     if (p->prec == GP_C128)
-        hipLaunchKernelGGL(k_scale<double>, dim3((unsigned)grid), dim3(256), 0, s, (double2 *)psi, p->npts,
-                           part, np, p->dV);
+        hipLaunchKernelGGL(k_scale<double>, dim3((unsigned)grid), dim3(256), 0, s, (double2 *)psi, p->npts, total,
+                           p->dV);
     else
-        hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)grid), dim3(256), 0, s, (float2 *)psi, p->npts,
-                           part, np, p->dV);
+        hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)grid), dim3(256), 0, s, (float2 *)psi, p->npts, total,
+                           p->dV);
+    timing_end(p, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s)
+{
+    timing_begin(p, K_NORM_FINAL, s);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, norm_partials(p, step_index),
+                       sweep_groups(p, p->ndim - 1), norm_total(p, step_index));
     timing_end(p, s);
     return hipGetLastError();
 }

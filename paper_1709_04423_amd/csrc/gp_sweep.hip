@@ -309,7 +309,15 @@ static hipError_t launch_window_d(const AxisPlan &A, const SweepParams &P, const
         case 4: launch_window<R, MODE, FLAGS, ACC, 4, 16>(A, P, tab, s); break;
         default: return hipErrorInvalidValue;
         }
-    } else {  // blocks of 4 points
+    } else if (A.B == 8) {  // blocks of 8 points (complex64 strided axes)
+        switch (A.D) {
+        case 1: launch_window<R, MODE, FLAGS, ACC, 1, 8>(A, P, tab, s); break;
+        case 2: launch_window<R, MODE, FLAGS, ACC, 2, 8>(A, P, tab, s); break;
+        case 3: launch_window<R, MODE, FLAGS, ACC, 3, 8>(A, P, tab, s); break;
+        case 4: launch_window<R, MODE, FLAGS, ACC, 4, 8>(A, P, tab, s); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {  // blocks of 4 points (complex128 strided axes)
         if (A.B != 4) return hipErrorInvalidValue;
         switch (A.D) {
         case 1: launch_window<R, MODE, FLAGS, ACC, 1, 4>(A, P, tab, s); break;
@@ -369,7 +377,7 @@ static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int fl
 int64_t sweep_groups(const gp_plan *p, int axis)
 {
     const AxisPlan &A = p->ax[axis];
-    if (axis == 0 && A.xq > 0) return (A.nlines + kXWavesPerGroup - 1) / kXWavesPerGroup;
+    if (axis == 0 && A.xq > 0) return (A.nlines + kXLinesPerGroup - 1) / kXLinesPerGroup;
     const int64_t g = (A.nlines + kLanes - 1) / kLanes;
     return A.K < 0 ? g : g * A.segs;
 }
@@ -409,11 +417,9 @@ hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int fl
     }
     P.ny = p->ndim >= 2 ? p->n[1] : 1;
     P.sched_axis = p->sched_axis;
-    const int parity = (int)(step_index & 1);
-    P.norm_in = p->d_norm + (1 - parity) * p->n_norm;
-    P.nnorm_in = (int)sweep_groups(p, p->ndim - 1);
+    P.norm_total = norm_total(p, step_index - 1);
     P.dV = p->dV;
-    P.norm_out = p->d_norm + parity * p->n_norm;
+    P.norm_out = norm_partials(p, step_index);
     P.adj_out = p->d_adj;
     const bool exact = A.K < 0;
     P.scan_steps = A.scan_steps;
@@ -424,6 +430,7 @@ hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int fl
     P.b_inf[0] = A.b_inf[0];
     P.b_inf[1] = sg * A.b_inf[1];
     P.b_inf[2] = sg * A.b_inf[2];
+    P.xmul = adjoint ? A.d_xmul_adj : A.d_xmul;
     // x lines are contiguous: coalesce through the LDS tile when ring + tile fit
     const bool tr = axis == 0;  // x lines too long for the scan kernel: coalesced through an LDS tile
     const void *tab = adjoint ? A.d_tab_adj : A.d_tab;

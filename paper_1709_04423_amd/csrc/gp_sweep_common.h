@@ -165,7 +165,7 @@ __device__ __forceinline__ LineCtx<R> line_setup(const SweepParams &P, int lane)
     const int64_t l = L.active ? line : 0;
     L.base = (l % P.m1) * P.s1 + (l / P.m1) * P.s2;
     L.scale = 1.0;
-    if (FLAGS & F_RENORM) L.scale = 1.0 / sqrt(P.dV * wave_sum_partials(P.norm_in, P.nnorm_in, lane));
+    if (FLAGS & F_RENORM) L.scale = 1.0 / sqrt(P.dV * P.norm_total[0]);
     L.vperp = R(0);
     L.hw0 = R(P.hw2[0]);
     L.ysq = R(0);

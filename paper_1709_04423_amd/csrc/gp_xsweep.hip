@@ -22,15 +22,13 @@ namespace gp {
 
 constexpr int kXWaves = kXWavesPerGroup;  // lines (wavefronts) per workgroup
 
-template <typename R>
-__device__ __forceinline__ cp<R> cmul(cp<R> a, cp<R> b)
+template <typename R> __device__ __forceinline__ cp<R> cmul(cp<R> a, cp<R> b)
 {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
-template <typename R>
-__device__ __forceinline__ cp<R> cfma(cp<R> a, cp<R> b, cp<R> c)  // a*b + c
+template <typename R> __device__ __forceinline__ cp<R> cfma(cp<R> a, cp<R> b, cp<R> c)  // a*b + c
 {
-    return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
 }
 template <typename R> __device__ __forceinline__ cp<R> shfl_up_c(cp<R> v, int d)
 {
@@ -62,6 +60,14 @@ __device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict
     }
 }
 
+// Each wavefront solves kXLines lines in turn.  Everything that depends only
+// on the position along the line is computed once: the table rows of the
+// lane's points are loaded before the line loop, and the multiplier halves of
+// the lane's composed maps at every scan step come precomputed from the host
+// (their products involve only the table), so per line only the data halves
+// (the F and G of the affine maps) are composed and scanned.
+constexpr int kXLines = kXLinesPerGroup / kXWavesPerGroup;
+
 template <typename R, int MODE, int FLAGS, int Q>
 __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P, const typename CT<R>::V *src,
                                                                    typename CT<R>::V *dst,
@@ -71,98 +77,105 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
     using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
-    const int64_t line = (int64_t)blockIdx.x * kXWaves + wave;
-    const bool active = line < P.nlines;
     const int64_t n = P.n;
-    const int64_t base = (active ? line : 0) * n;
     const int64_t q0 = (int64_t)lane * Q;
+    const int S = P.scan_steps;
+    const cp<R> zero = {R(0), R(0)};
 
-    LineCtx<R> L = line_ctx_of<R>(P, active ? line : 0);
-    if (FLAGS & F_RENORM) L.scale = 1.0 / sqrt(P.dV * wave_sum_partials(P.norm_in, P.nnorm_in, lane));
-
-    // load Q consecutive points (one contiguous segment per wavefront)
-    cp<R> u[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t q = q0 + i;
-        u[i] = (active && q < n) ? from_v<R>(src[base + q]) : cp<R>{R(0), R(0)};
-        if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
-    }
-    // neighbours across lane boundaries (zero ghosts at the line ends)
-    cp<R> left = shfl_up_c(u[Q - 1], 1);
-    cp<R> right = shfl_down_c(u[0], 1);
-    if (lane == 0) left = {R(0), R(0)};
-    if (lane == kLanes - 1) right = {R(0), R(0)};
-
-    // forward maps y_p = a_p y_{p-1} + f_p with a_p = -c'_p, f_p = c'_p rhs_p
-    cp<R> cc[Q], f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        V c, b, blo;
-        row_of<R>(P, tab, q0 + i, c, b, blo);
-        const cp<R> um1 = i == 0 ? left : u[i - 1];
-        const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
-        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
-        cc[i] = from_v<R>(c);
-        f[i] = cmul(cc[i], rhs);
-    }
-    // compose this lane's maps: y_last = A y_in + F
-    cp<R> A = {-cc[0].re, -cc[0].im}, F = f[0];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const cp<R> a = {-cc[i].re, -cc[i].im};
-        F = cfma(a, F, f[i]);
-        A = cmul(a, A);
-    }
-    for (int s = 0; s < P.scan_steps; ++s) {
-        const int d = 1 << s;
-        const cp<R> Ap = shfl_up_c(A, d), Fp = shfl_up_c(F, d);
-        if (lane >= d) {
-            F = cfma(A, Fp, F);
-            A = cmul(A, Ap);
-        }
-    }
-    cp<R> y = shfl_up_c(F, 1);
-    if (lane == 0) y = {R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        y = cfma({-cc[i].re, -cc[i].im}, y, f[i]);
-        f[i] = y;  // f now holds the eliminated values y_p
-    }
-    // backward maps u'_p = b_p u'_{p+1} + y_p with b_p = -c'_p, composed from the top
-    cp<R> Bm = {-cc[Q - 1].re, -cc[Q - 1].im}, G = f[Q - 1];
-#pragma unroll
-    for (int i = Q - 2; i >= 0; --i) {
-        const cp<R> b = {-cc[i].re, -cc[i].im};
-        G = cfma(b, G, f[i]);
-        Bm = cmul(b, Bm);
-    }
-    for (int s = 0; s < P.scan_steps; ++s) {
-        const int d = 1 << s;
-        const cp<R> Bp = shfl_down_c(Bm, d), Gp = shfl_down_c(G, d);
-        if (lane + d < kLanes) {
-            G = cfma(Bm, Gp, G);
-            Bm = cmul(Bm, Bp);
-        }
-    }
-    cp<R> v = shfl_down_c(G, 1);
-    if (lane == kLanes - 1) v = {R(0), R(0)};
-#pragma unroll
-    for (int i = Q - 1; i >= 0; --i) {
-        v = cfma({-cc[i].re, -cc[i].im}, v, f[i]);
-        u[i] = v;
-    }
-
-    // epilogue and store
+    // multipliers of this lane's composed maps before each scan step (host table:
+    // rows s = 0..5 forward, 6..11 backward, one value per lane)
+    const V *__restrict__ xmul = (const V *)P.xmul;
+    const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
     double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
+    const int64_t first = ((int64_t)blockIdx.x * kXWaves + wave) * kXLines;
+    V nxt[Q];  // the next line's values, loaded while the current one is solved
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t q = q0 + i;
-        if (active && q < n) {
-            cp<R> w = u[i];
-            if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
-            if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, q, state, base + q, P, L, acc_w, acc_g);
-            dst[base + q] = to_v<V>(w);
+    for (int i = 0; i < Q; ++i)
+        nxt[i] = (first < P.nlines && q0 + i < n) ? src[first * n + q0 + i] : to_v<V>(zero);
+#pragma unroll 1
+    for (int li = 0; li < kXLines; ++li) {
+        const int64_t line = first + li;
+        if (line >= P.nlines) break;  // uniform across the wavefront
+        const int64_t base = line * n;
+        LineCtx<R> L = line_ctx_of<R>(P, line);
+        if (FLAGS & F_RENORM) L.scale = renorm;
+
+        cp<R> u[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) u[i] = from_v<R>(nxt[i]);
+        if (li + 1 < kXLines) {
+            const int64_t nl = line + 1;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                nxt[i] = (nl < P.nlines && q0 + i < n) ? src[nl * n + q0 + i] : to_v<V>(zero);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t q = q0 + i;
+            if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
+        }
+        cp<R> left = shfl_up_c(u[Q - 1], 1);
+        cp<R> right = shfl_down_c(u[0], 1);
+        if (lane == 0) left = zero;
+        if (lane == kLanes - 1) right = zero;
+
+        // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
+        // table rows: kernel-argument constants except on the first few lanes
+        cp<R> f[Q], ac[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const cp<R> um1 = i == 0 ? left : u[i - 1];
+            const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
+            V c, b, blo;
+            row_of<R>(P, tab, q0 + i, c, b, blo);
+            const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
+            f[i] = cmul(from_v<R>(c), rhs);
+            ac[i] = {-c.x, -c.y};
+        }
+        cp<R> F = f[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) F = cfma(ac[i], F, f[i]);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s < S) {  // uniform
+                const cp<R> Fp = shfl_up_c(F, 1 << s);
+                if (lane >= (1 << s)) F = cfma(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
+            }
+        }
+        cp<R> y = shfl_up_c(F, 1);
+        if (lane == 0) y = zero;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            y = cfma(ac[i], y, f[i]);
+            f[i] = y;
+        }
+        // backward: u'_p = a_p u'_{p+1} + y_p
+        cp<R> G = f[Q - 1];
+#pragma unroll
+        for (int i = Q - 2; i >= 0; --i) G = cfma(ac[i], G, f[i]);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s < S) {  // uniform
+                const cp<R> Gp = shfl_down_c(G, 1 << s);
+                if (lane + (1 << s) < kLanes) G = cfma(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
+            }
+        }
+        cp<R> v = shfl_down_c(G, 1);
+        if (lane == kLanes - 1) v = zero;
+#pragma unroll
+        for (int i = Q - 1; i >= 0; --i) {
+            v = cfma(ac[i], v, f[i]);
+            u[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t q = q0 + i;
+            if (q < n) {
+                cp<R> w = u[i];
+                if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
+                if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, q, state, base + q, P, L, acc_w, acc_g);
+                dst[base + q] = to_v<V>(w);
+            }
         }
     }
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
@@ -196,7 +209,8 @@ template <typename R, int MODE, int FLAGS, int Q>
 static void launch_q(const SweepParams &P, const void *tab, hipStream_t s)
 {
     using V = typename CT<R>::V;
-    const unsigned grid = (unsigned)((P.nlines + kXWaves - 1) / kXWaves);
+    const int64_t per_group = (int64_t)kXWaves * kXLines;
+    const unsigned grid = (unsigned)((P.nlines + per_group - 1) / per_group);
     hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
                        (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
 }
