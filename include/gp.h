@@ -162,23 +162,45 @@ gp_status gp_step_adjoint(gp_plan *plan, const void *states, void *lambda, int64
 
 /* ------------------------------------------------------ batched form */
 
-/* A batch of `count` independent 2D problems (grids n[k][0..1], spacings
- * dx[k] (same on both axes), steps dt[k], traps omega[k][0..1], g[k]), all in
- * one mode and precision, advanced together by gp_batch_step in one
- * persistent launch.  Plans are built per problem as in gp_plan_create. */
+/* A batch of `count` independent 2D problems (problem k: grid n[2k], n[2k+1]
+ * (x first, each 1..1024), spacing dx[k] on both axes, step dt[k], trap
+ * omega[2k], omega[2k+1], nonlinearity g[k]), all in one mode and precision.
+ * Each problem gets a plan as from gp_plan_create; the batch advances them
+ * together (gp_batch_step), either with two launches per step (all problems'
+ * x sweeps, then all y sweeps) or, in real time, with one persistent launch
+ * for all steps whose wavefronts take (step, phase, problem, tile) items from
+ * a device queue and wait on per-problem completion counters.
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
 gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n /* [count][2] */,
                           const double *dx, const double *dt, gp_mode mode,
                           const double *omega /* [count][2] */, const double *g, gp_prec prec);
 gp_status gp_batch_destroy(gp_batch *batch);
 
-/* Advance every problem k (psis[k]: device pointer of problem k's grid) by
- * nsteps steps.  The pointer array is host memory.  Asynchronous. */
+/* Advance every problem k (psis[k]: device grid of problem k, layout as
+ * gp_step's) by nsteps steps; the pointer array is host memory.  Imaginary
+ * time renormalises every problem to unit norm.  Asynchronous, except that a
+ * persistent launch synchronises `stream` to read its error flag: a bounded
+ * device-side dependency wait that gave up yields GP_ETIMEOUT (the grids are
+ * then not advanced consistently). */
 gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream);
 
-/* Time the candidate tile shapes of the batch kernel on scratch copies of the
- * problems and keep the fastest; cache_path (may be NULL) is a text file of
- * previous results keyed by problem size, read first and updated.  Synchronises. */
+/* Time candidate configurations -- persistent or phased launch, x lines per
+ * work item (1, 2, 4), y segments per line (1, 2, 4, 8), persistent grid size
+ * (256..2048 workgroups) -- for 10 steps each on scratch copies of the problems
+ * and keep the fastest.  cache_path (may be NULL): text file of previous
+ * results, one line "key persistent lines ysegs grid" per batch shape (key: the
+ * precision, mode and sorted problem sizes); read first, appended to.
+ * Synchronises `stream`. */
 gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *stream);
+
+/* Bound, in polls (each a short sleep), of one dependency wait in the
+ * persistent launch (default 2^22, about 0.3 s): for callers that must bound a
+ * stalled launch, and for exercising the GP_ETIMEOUT path. */
+gp_status gp_batch_set_wait_limit(gp_batch *batch, uint32_t polls);
+
+/* Read / set the configuration explicitly (persistent = 1 needs real time). */
+gp_status gp_batch_get_config(const gp_batch *batch, int *persistent, int *lines, int *ysegs, int *grid);
+gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ysegs, int grid);
 
 /* Observables of problem k of a batch (as gp_observables). */
 gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream);

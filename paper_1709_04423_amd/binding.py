@@ -78,6 +78,10 @@ def lib():
             "gp_batch_step": [vp, pp, i64, vp],
             "gp_batch_autotune": [vp, ctypes.c_char_p, vp],
             "gp_batch_observables": [vp, i32, vp, ctypes.POINTER(GpObs), vp],
+            "gp_batch_get_config": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)],
+            "gp_batch_set_config": [vp, i32, i32, i32, i32],
+            "gp_batch_set_wait_limit": [vp, ctypes.c_uint32],
             "gp_plan_timing_enable": [vp, i64],
             "gp_plan_timing_read": [vp, c_i64p, c_dp],
             "gp_copy_probe": [vp, vp, i64, vp],
@@ -237,6 +241,74 @@ class Plan:
         check(lib().gp_plan_timing_read(self._h, counts, ms), "gp_plan_timing_read")
         names = kernel_names()
         return {names[k]: (counts[k], ms[k]) for k in range(GP_NUM_KERNEL_KINDS) if counts[k]}
+
+
+class Batch:
+    """Owns a gp_batch of independent 2D problems (sizes x first)."""
+
+    def __init__(self, sizes, dx, dt, mode, omega, g, prec=GP_C64):
+        import numpy as np
+        L = lib()
+        self.count = len(sizes)
+        self.sizes = [tuple(int(v) for v in s) for s in sizes]
+        self.prec = int(prec)
+        n = np.ascontiguousarray(np.array(self.sizes, dtype=np.int64).reshape(-1))
+        dxa = np.ascontiguousarray(np.broadcast_to(np.asarray(dx, dtype=np.float64), (self.count,)))
+        dta = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.count,)))
+        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(self.count, 2).reshape(-1))
+        ga = np.ascontiguousarray(np.broadcast_to(np.asarray(g, dtype=np.float64), (self.count,)))
+        h = ctypes.c_void_p()
+        check(L.gp_batch_create(ctypes.byref(h), self.count, n.ctypes.data_as(c_i64p), dxa.ctypes.data_as(c_dp),
+                                dta.ctypes.data_as(c_dp), int(mode), om.ctypes.data_as(c_dp),
+                                ga.ctypes.data_as(c_dp), self.prec), "gp_batch_create")
+        self._h = h
+
+    def shape(self, k):
+        return self.sizes[k][::-1]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().gp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, psis, nsteps=1, stream=None):
+        if len(psis) != self.count:
+            raise ValueError("one grid per problem")
+        for k, p in enumerate(psis):
+            _check_psi(p, self.shape(k), self.prec)
+        arr = (ctypes.c_void_p * self.count)(*[p.data_ptr() for p in psis])
+        check(lib().gp_batch_step(self._h, arr, int(nsteps), _stream_handle(stream)), "gp_batch_step")
+        return psis
+
+    def autotune(self, cache_path=None, stream=None):
+        check(lib().gp_batch_autotune(self._h, cache_path.encode() if cache_path else None, _stream_handle(stream)),
+              "gp_batch_autotune")
+        return self.config()
+
+    def config(self):
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib().gp_batch_get_config(self._h, *[ctypes.byref(x) for x in v]), "gp_batch_get_config")
+        return {"persistent": v[0].value, "lines": v[1].value, "ysegs": v[2].value, "grid": v[3].value}
+
+    def set_config(self, persistent=0, lines=4, ysegs=4, grid=1024):
+        check(lib().gp_batch_set_config(self._h, int(persistent), int(lines), int(ysegs), int(grid)),
+              "gp_batch_set_config")
+
+    def set_wait_limit(self, polls):
+        check(lib().gp_batch_set_wait_limit(self._h, int(polls)), "gp_batch_set_wait_limit")
+
+    def observables(self, k, psi, stream=None):
+        _check_psi(psi, self.shape(k), self.prec)
+        o = GpObs()
+        check(lib().gp_batch_observables(self._h, int(k), ctypes.c_void_p(psi.data_ptr()), ctypes.byref(o),
+                                         _stream_handle(stream)), "gp_batch_observables")
+        return o.as_dict()
 
 
 def thomas_table(n: int, dx: float, dt: float, mode: int, prec: int = GP_C128, adjoint: bool = False):

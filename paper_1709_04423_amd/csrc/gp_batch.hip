@@ -1,37 +1,664 @@
-// Batched form: many independent 2D problems advanced together.
+// Batched form: many independent 2D SSCN problems of different sizes advanced
+// together.
+//
+// Every problem keeps its own plan (tables, work grid, partial buffers); the
+// batch adds per-problem sweep parameters in device memory and lists of
+// wavefront-sized work items:
+//   x items  (problem, first line, count): count x lines, one wavefront (scan solver),
+//   y items  (problem, 64-column group, segment): one wavefront (windowed solver).
+// A step is the x items of every problem followed by the y items of every
+// problem.  Two ways to run nsteps steps:
+//   - phased: two launches per step (all x items, then all y items);
+//   - persistent (real time): ONE launch; each wavefront pops items from a
+//     device queue ordered by (step, phase) and, before working on an item,
+//     waits until its problem's items of the previous phase are done (per-
+//     problem completion counters).  Every item depends only on items earlier
+//     in the queue, all of which were taken by running wavefronts, so the
+//     queue drains without deadlock whatever the grid size.  Waits are bounded:
+//     past the limit the wavefront raises an error flag, every wavefront stops
+//     taking items, the launch ends, and gp_batch_step returns GP_ETIMEOUT.
+// The autotuner picks the run mode, lines per x item, y segments and the
+// persistent grid size by timing candidates on scratch copies.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "gp_internal.h"
+#include "gp_sweep_common.h"
+#include "gp_window.h"
+#include "gp_xscan.h"
+
+namespace gp {
+
+struct BatchItem {
+    int prob;
+    int seg;    // y: segment index; x: unused
+    int segs;   // y: segments of this problem's lines; x: unused
+    int count;  // x: lines in the item; y: unused
+    int64_t first;  // x: first line; y: 64-column group
+};
+
+// Counters of the persistent launch: queue head, error flag, then per problem
+// the number of finished x items and y items (monotonic over the launch).
+constexpr int kCtrHead = 0, kCtrError = 1, kCtrFirstProblem = 4;
+constexpr int kBatchWaves = 4;                 // wavefronts per workgroup of the batched kernels
+constexpr unsigned kSpinLimit = 1u << 22;      // default bound of a dependency wait (polls, ~0.3 s)
+
+struct BatchConfig {
+    int persistent = 0;  // 1: one launch for all steps (real time only)
+    int lines = 4;       // x lines per item
+    int ysegs = 4;       // y segments per line (capped per problem)
+    int grid = 1024;     // workgroups of the persistent launch
+    unsigned spin_limit = kSpinLimit;  // polls before a dependency wait gives up
+};
+
+}  // namespace gp
+
+struct gp_batch {
+    int count = 0;
+    gp_mode mode = GP_REAL;
+    gp_prec prec = GP_C64;
+    int device = 0;
+    std::vector<gp_plan *> plans;
+    gp::BatchConfig cfg;
+    // device data, rebuilt by prepare()
+    gp::SweepParams *d_px = nullptr, *d_py = nullptr;
+    gp::BatchItem *d_xi = nullptr, *d_yi = nullptr;
+    int64_t nxi = 0, nyi = 0;
+    int *d_ctr = nullptr;          // kCtrFirstProblem + 2 * count ints
+    int *d_nx_per = nullptr, *d_ny_per = nullptr;
+    int64_t *d_nparts = nullptr;   // y partials per problem (imaginary-time norm)
+    size_t lds_wave = 0;           // ring bytes of one y wavefront (largest problem)
+    int qmax = 1;                  // largest x points per lane over the problems
+    std::vector<const void *> bound; // psi pointers the device parameters were built for
+    int bound_cfg_lines = -1, bound_cfg_ysegs = -1;
+};
+
+namespace gp {
+
+static __device__ __forceinline__ int wave_first_lane_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------ item bodies
+
+// QMAX: the largest points-per-lane of the batch's x lines; only the solver
+// variants up to it are compiled into a kernel (their registers would be
+// allocated even when not taken).
+template <typename R, int MODE, int FLAGS, int QMAX>
+__device__ __forceinline__ void run_x_item(const SweepParams &P0, const BatchItem &it, int64_t step)
+{
+    using V = typename CT<R>::V;
+    SweepParams P = P0;
+    P.norm_total = P0.norm_total + ((step - 1) & 1);
+    double a = 0.0, b = 0.0, c = 0.0;
+    const V *src = (const V *)P.psi;
+    V *dst = (V *)P.out;
+    const V *tab = (const V *)P.tab;
+    if (P.xq == 1) x_scan_wave<R, MODE, FLAGS, 1>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+    else if (P.xq == 2) x_scan_wave<R, MODE, FLAGS, 2>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+    else if constexpr (QMAX >= 4) {
+        if (P.xq == 4) x_scan_wave<R, MODE, FLAGS, 4>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+        else if constexpr (QMAX >= 8) {
+            if (P.xq == 8) x_scan_wave<R, MODE, FLAGS, 8>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+            else if constexpr (QMAX >= 16) {
+                if (P.xq == 16) x_scan_wave<R, MODE, FLAGS, 16>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+            }
+        }
+    }
+}
+
+template <typename R, int MODE, int FLAGS>
+__device__ __forceinline__ void run_y_item(const SweepParams &P0, const BatchItem &it, int64_t step, char *lds)
+{
+    using V = typename CT<R>::V;
+    SweepParams P = P0;
+    P.norm_out = P0.norm_out + (step & 1) * P0.n_norm;
+    const V *src = (const V *)P.psi;
+    V *dst = (V *)P.out;
+    const V *tab = (const V *)P.tab;
+    const int64_t ngroups = (P.nlines + kLanes - 1) / kLanes;
+    const int64_t part = it.first + ngroups * it.seg;
+    switch (P.D) {
+    case 1: window_run<R, MODE, FLAGS, kStrided, 1, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 2: window_run<R, MODE, FLAGS, kStrided, 2, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 3: window_run<R, MODE, FLAGS, kStrided, 3, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 4: window_run<R, MODE, FLAGS, kStrided, 4, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 5: window_run<R, MODE, FLAGS, kStrided, 5, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 6: window_run<R, MODE, FLAGS, kStrided, 6, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 7: window_run<R, MODE, FLAGS, kStrided, 7, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    case 8: window_run<R, MODE, FLAGS, kStrided, 8, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
+    default: break;
+    }
+}
+
+// ------------------------------------------------------------ phased kernels
+
+template <typename R, int MODE, int QMAX>
+__global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_x(const SweepParams *__restrict__ px,
+                                                                  const BatchItem *__restrict__ items, int64_t nitems,
+                                                                  int64_t step, int renorm)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBatchWaves + wave_first_lane_i(threadIdx.x / kLanes);
+    if (i >= nitems) return;  // whole wavefront
+    const BatchItem it = items[i];
+    if (MODE == GP_IMAG && renorm)
+        run_x_item<R, MODE, F_FUSE_N | F_RENORM, QMAX>(px[it.prob], it, step);
+    else
+        run_x_item<R, MODE, F_FUSE_N, QMAX>(px[it.prob], it, step);
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_y(const SweepParams *__restrict__ py,
+                                                                  const BatchItem *__restrict__ items, int64_t nitems,
+                                                                  int64_t step, size_t lds_wave)
+{
+    extern __shared__ char lds_raw[];
+    const int w = wave_first_lane_i(threadIdx.x / kLanes);
+    const int64_t i = (int64_t)blockIdx.x * kBatchWaves + w;
+    if (i >= nitems) return;
+    const BatchItem it = items[i];
+    run_y_item<R, MODE, MODE == GP_IMAG ? F_NORM_OUT : 0>(py[it.prob], it, step, lds_raw + (size_t)w * lds_wave);
+}
+
+// Per problem: sum of its y partials of `step` (fixed order) into its norm total.
+__global__ __launch_bounds__(256) void k_batch_norm_final(const SweepParams *__restrict__ py,
+                                                          const int64_t *__restrict__ nparts, int64_t step)
+{
+    __shared__ double lds[256 / kLanes];
+    const SweepParams &P = py[blockIdx.x];
+    const double *part = P.norm_out + (step & 1) * P.n_norm;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts[blockIdx.x]; i += blockDim.x) acc += part[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & (kLanes - 1)) == 0) lds[threadIdx.x / kLanes] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 256 / kLanes; ++w) s += lds[w];
+        // the x parameters read totals at P.norm_total + parity; y and x share the plan's buffer
+        const_cast<double *>(P.norm_total)[step & 1] = s;
+    }
+}
+
+// Per problem: psi <- psi / sqrt(dV * total of the last step).
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_scale(const SweepParams *__restrict__ py, int64_t last_step)
+{
+    using V = typename CT<R>::V;
+    const SweepParams &P = py[blockIdx.x];
+    const double s = 1.0 / sqrt(P.dV * P.norm_total[last_step & 1]);
+    V *psi = (V *)P.out;
+    const int64_t npts = P.n * P.nlines;
+    for (int64_t i = threadIdx.x; i < npts; i += blockDim.x) {
+        V v = psi[i];
+        v.x = R((double)v.x * s);
+        v.y = R((double)v.y * s);
+        psi[i] = v;
+    }
+}
+
+__global__ void k_fill_zero_i32(int *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ------------------------------------------------------------ persistent kernel
+
+__device__ __forceinline__ bool wait_at_least(int *ctr, int target, int *error, unsigned limit)
+{
+    // lane 0 polls; the result is broadcast so the wavefront takes one branch
+    int ok = 1;
+    if ((threadIdx.x & (kLanes - 1)) == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (++spins > limit) {
+                __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    ok = __shfl(ok, 0, kLanes);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the producers' grid writes
+    return ok != 0;
+}
+
+template <typename R, int QMAX>
+__global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
+    const SweepParams *__restrict__ px, const SweepParams *__restrict__ py, const BatchItem *__restrict__ xi,
+    int64_t nxi, const BatchItem *__restrict__ yi, int64_t nyi, const int *__restrict__ nx_per,
+    const int *__restrict__ ny_per, int64_t step0, int64_t nsteps, int *ctr, size_t lds_wave, unsigned limit)
+{
+    extern __shared__ char lds_raw[];
+    const int w = wave_first_lane_i(threadIdx.x / kLanes);
+    char *lds = lds_raw + (size_t)w * lds_wave;
+    int *error = ctr + kCtrError;
+    int *xdone = ctr + kCtrFirstProblem;
+    const int64_t per_step = nxi + nyi;
+    const int64_t total = per_step * nsteps;
+    for (;;) {
+        int64_t item = 0;
+        if ((threadIdx.x & (kLanes - 1)) == 0)
+            item = __hip_atomic_fetch_add(ctr + kCtrHead, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        item = __shfl(item, 0, kLanes);
+        if (item >= total) break;
+        if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        const int64_t sl = item / per_step;  // step within this launch
+        const int64_t r = item - sl * per_step;
+        if (r < nxi) {
+            const BatchItem it = xi[r];
+            int *ydone = xdone + 1;
+            // the previous step's y items of this problem are done
+            if (!wait_at_least(ydone + 2 * it.prob, (int)(sl * ny_per[it.prob]), error, limit)) break;
+            run_x_item<R, GP_REAL, F_FUSE_N, QMAX>(px[it.prob], it, step0 + sl);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if ((threadIdx.x & (kLanes - 1)) == 0)
+                __hip_atomic_fetch_add(xdone + 2 * it.prob, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const BatchItem it = yi[r - nxi];
+            // this step's x items of this problem are done
+            if (!wait_at_least(xdone + 2 * it.prob, (int)((sl + 1) * nx_per[it.prob]), error, limit)) break;
+            run_y_item<R, GP_REAL, 0>(py[it.prob], it, step0 + sl, lds);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if ((threadIdx.x & (kLanes - 1)) == 0)
+                __hip_atomic_fetch_add(xdone + 2 * it.prob + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+static void free_batch_device(gp_batch *b)
+{
+    hipFree(b->d_px);
+    hipFree(b->d_py);
+    hipFree(b->d_xi);
+    hipFree(b->d_yi);
+    hipFree(b->d_ctr);
+    hipFree(b->d_nx_per);
+    hipFree(b->d_ny_per);
+    hipFree(b->d_nparts);
+    b->d_px = b->d_py = nullptr;
+    b->d_xi = b->d_yi = nullptr;
+    b->d_ctr = b->d_nx_per = b->d_ny_per = nullptr;
+    b->d_nparts = nullptr;
+}
+
+static gp_status upload(void **dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMalloc(dst, bytes > 0 ? bytes : 16);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch)");
+    if (bytes > 0 && src) {  // src NULL: allocation only (filled on the device before use)
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(batch)");
+    }
+    return GP_OK;
+}
+
+// y segments of problem k: at most the plan's count, each segment at least
+// four windows long.
+static int y_segments(const gp_plan *p, int want)
+{
+    const AxisPlan &A = p->ax[1];
+    if (A.K < 0) return 1;
+    return std::max(1, std::min(want, A.segs));
+}
+
+// (Re)build the device parameters and item lists for psis and the current config.
+static gp_status prepare(gp_batch *b, void *const *psis)
+{
+    bool same = (int)b->bound.size() == b->count && b->bound_cfg_lines == b->cfg.lines &&
+                b->bound_cfg_ysegs == b->cfg.ysegs;
+    for (int k = 0; same && k < b->count; ++k) same = b->bound[k] == psis[k];
+    if (same) return GP_OK;
+    free_batch_device(b);
+    std::vector<SweepParams> px(b->count), py(b->count);
+    std::vector<BatchItem> xi, yi;
+    std::vector<int> nx_per(b->count), ny_per(b->count);
+    std::vector<int64_t> nparts(b->count);
+    size_t lds_wave = 0;
+    for (int k = 0; k < b->count; ++k) {
+        gp_plan *p = b->plans[k];
+        // 2D: x psi -> work, y work -> psi
+        px[k] = make_sweep_params(p, 0, psis[k], p->d_work, false, 0, nullptr);
+        py[k] = make_sweep_params(p, 1, p->d_work, psis[k], false, 0, nullptr);
+        px[k].norm_total = norm_total(p, 0);  // parity offsets are added in the kernels
+        py[k].norm_total = norm_total(p, 0);
+        py[k].norm_out = norm_partials(p, 0);
+        const int64_t ny = p->n[1], nx = p->n[0];
+        int cnt = 0;
+        for (int64_t l = 0; l < ny; l += b->cfg.lines) {
+            xi.push_back({k, 0, 1, (int)std::min<int64_t>(b->cfg.lines, ny - l), l});
+            ++cnt;
+        }
+        nx_per[k] = cnt;
+        const int segs = y_segments(p, b->cfg.ysegs);
+        const int64_t groups = (nx + kLanes - 1) / kLanes;
+        cnt = 0;
+        for (int s = 0; s < segs; ++s)
+            for (int64_t g = 0; g < groups; ++g) {
+                yi.push_back({k, s, segs, 0, g});
+                ++cnt;
+            }
+        ny_per[k] = cnt;
+        nparts[k] = groups * segs;
+        lds_wave = std::max(lds_wave, b->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(p->ax[1].L)
+                                                         : window_lds_bytes<float, kStrided, 4>(p->ax[1].L));
+    }
+    gp_status st = upload((void **)&b->d_px, px.data(), px.size() * sizeof(SweepParams));
+    if (st == GP_OK) st = upload((void **)&b->d_py, py.data(), py.size() * sizeof(SweepParams));
+    if (st == GP_OK) st = upload((void **)&b->d_xi, xi.data(), xi.size() * sizeof(BatchItem));
+    if (st == GP_OK) st = upload((void **)&b->d_yi, yi.data(), yi.size() * sizeof(BatchItem));
+    if (st == GP_OK) st = upload((void **)&b->d_nx_per, nx_per.data(), nx_per.size() * sizeof(int));
+    if (st == GP_OK) st = upload((void **)&b->d_ny_per, ny_per.data(), ny_per.size() * sizeof(int));
+    if (st == GP_OK) st = upload((void **)&b->d_nparts, nparts.data(), nparts.size() * sizeof(int64_t));
+    if (st == GP_OK) st = upload((void **)&b->d_ctr, nullptr, (kCtrFirstProblem + 2 * b->count) * sizeof(int));
+    if (st != GP_OK) {
+        free_batch_device(b);
+        return st;
+    }
+    b->nxi = (int64_t)xi.size();
+    b->nyi = (int64_t)yi.size();
+    b->lds_wave = lds_wave;
+    b->bound.assign(psis, psis + b->count);
+    b->bound_cfg_lines = b->cfg.lines;
+    b->bound_cfg_ysegs = b->cfg.ysegs;
+    return GP_OK;
+}
+
+template <typename R, int MODE, int QMAX>
+static hipError_t run_phased(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    const unsigned gx = (unsigned)((b->nxi + kBatchWaves - 1) / kBatchWaves);
+    const unsigned gy = (unsigned)((b->nyi + kBatchWaves - 1) / kBatchWaves);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = step0 + k;
+        hipLaunchKernelGGL((k_batch_x<R, MODE, QMAX>), dim3(gx), dim3(kLanes * kBatchWaves), 0, s, b->d_px, b->d_xi, b->nxi,
+                           n, (int)(k > 0));
+        hipLaunchKernelGGL((k_batch_y<R, MODE>), dim3(gy), dim3(kLanes * kBatchWaves), kBatchWaves * b->lds_wave, s,
+                           b->d_py, b->d_yi, b->nyi, n, b->lds_wave);
+        if (MODE == GP_IMAG)
+            hipLaunchKernelGGL(k_batch_norm_final, dim3(b->count), dim3(256), 0, s, b->d_py, b->d_nparts, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (MODE == GP_IMAG)
+        hipLaunchKernelGGL((k_batch_scale<R>), dim3(b->count), dim3(256), 0, s, b->d_py, step0 + nsteps - 1);
+    return hipGetLastError();
+}
+
+template <typename R, int QMAX>
+static hipError_t run_persistent(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    // the queue head and the per-problem counters are 32-bit: launches of at most 2^30 items
+    const int64_t per_step = b->nxi + b->nyi;
+    const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / per_step);
+    const int64_t nctr = kCtrFirstProblem + 2 * b->count;
+    for (int64_t k0 = 0; k0 < nsteps; k0 += chunk) {
+        const int64_t m = std::min(chunk, nsteps - k0);
+        hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b->d_ctr, nctr);
+        hipLaunchKernelGGL((k_batch_persistent<R, QMAX>), dim3((unsigned)b->cfg.grid), dim3(kLanes * kBatchWaves),
+                           kBatchWaves * b->lds_wave, s, b->d_px, b->d_py, b->d_xi, b->nxi, b->d_yi, b->nyi,
+                           b->d_nx_per, b->d_ny_per, step0 + k0, m, b->d_ctr, b->lds_wave, b->cfg.spin_limit);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename R, int QMAX>
+static hipError_t run_batch_q(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    if (b->cfg.persistent && b->mode == GP_REAL) return run_persistent<R, QMAX>(b, step0, nsteps, s);
+    return b->mode == GP_IMAG ? run_phased<R, GP_IMAG, QMAX>(b, step0, nsteps, s)
+                              : run_phased<R, GP_REAL, QMAX>(b, step0, nsteps, s);
+}
+
+template <typename R>
+static hipError_t run_batch_r(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    if (b->qmax <= 2) return run_batch_q<R, 2>(b, step0, nsteps, s);
+    if (b->qmax <= 4) return run_batch_q<R, 4>(b, step0, nsteps, s);
+    if (b->qmax <= 8) return run_batch_q<R, 8>(b, step0, nsteps, s);
+    return run_batch_q<R, 16>(b, step0, nsteps, s);
+}
+
+static hipError_t run_batch(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    return b->prec == GP_C128 ? run_batch_r<double>(b, step0, nsteps, s) : run_batch_r<float>(b, step0, nsteps, s);
+}
+
+static gp_status check_error_flag(gp_batch *b, hipStream_t s)
+{
+    if (!(b->cfg.persistent && b->mode == GP_REAL)) return GP_OK;
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, b->d_ctr + kCtrError, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch error flag");
+    if (flag) {
+        set_error("persistent batch launch: a dependency wait exceeded its bound");
+        return GP_ETIMEOUT;
+    }
+    return GP_OK;
+}
+
+static std::string cache_key(const gp_batch *b)
+{
+    std::vector<std::string> sizes;
+    for (const gp_plan *p : b->plans) sizes.push_back(std::to_string(p->n[0]) + "x" + std::to_string(p->n[1]));
+    std::sort(sizes.begin(), sizes.end());
+    std::ostringstream os;
+    os << (b->prec == GP_C128 ? "c128" : "c64") << (b->mode == GP_REAL ? "-real" : "-imag");
+    for (const std::string &z : sizes) os << "-" << z;
+    return os.str();
+}
+
+}  // namespace gp
+
+using namespace gp;
 
 extern "C" {
 
 gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n, const double *dx, const double *dt,
                           gp_mode mode, const double *omega, const double *g, gp_prec prec)
 {
-    (void)mode; (void)prec;
-    if (!out || count < 1 || !n || !dx || !dt || !omega || !g) return gp::set_error("bad argument"), GP_EINVAL;
+    if (!out || count < 1 || !n || !dx || !dt || !omega || !g) return set_error("bad argument"), GP_EINVAL;
     *out = nullptr;
-    gp::set_error("batch form not built yet");
-    return GP_EUNSUPPORTED;
+    if (mode != GP_IMAG && mode != GP_REAL) return set_error("bad mode"), GP_EINVAL;
+    if (prec != GP_C128 && prec != GP_C64) return set_error("bad precision"), GP_EINVAL;
+    for (int k = 0; k < count; ++k)
+        if (n[2 * k] < 1 || n[2 * k + 1] < 1 || n[2 * k] > 64 * kXMaxQ)
+            return set_error("batch problems need 1 <= n <= 1024 per axis"), GP_EINVAL;
+    gp_batch *b = new (std::nothrow) gp_batch();
+    if (!b) return set_error("host allocation failed"), GP_ENOMEM;
+    b->count = count;
+    b->mode = mode;
+    b->prec = prec;
+    hipGetDevice(&b->device);
+    for (int k = 0; k < count; ++k) {
+        gp_trap trap{};
+        trap.omega[0] = omega[2 * k];
+        trap.omega[1] = omega[2 * k + 1];
+        const double dxs[2] = {dx[k], dx[k]};
+        gp_plan *p = nullptr;
+        gp_status st = gp_plan_create(&p, 2, n + 2 * k, dxs, dt[k], mode, &trap, g[k], prec);
+        if (st != GP_OK) {
+            gp_batch_destroy(b);
+            return st;
+        }
+        b->plans.push_back(p);
+        b->qmax = std::max(b->qmax, p->ax[0].xq);
+    }
+    *out = b;
+    return GP_OK;
 }
 
-gp_status gp_batch_destroy(gp_batch *batch) { (void)batch; return GP_OK; }
-
-gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream)
+gp_status gp_batch_destroy(gp_batch *b)
 {
-    (void)stream;
-    if (!batch || !psis || nsteps < 0) return gp::set_error("bad argument"), GP_EINVAL;
-    return GP_EUNSUPPORTED;
+    if (!b) return GP_OK;
+    free_batch_device(b);
+    for (gp_plan *p : b->plans) gp_plan_destroy(p);
+    delete b;
+    return GP_OK;
 }
 
-gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *stream)
+gp_status gp_batch_step(gp_batch *b, void *const *psis, int64_t nsteps, void *stream)
 {
-    (void)batch; (void)cache_path; (void)stream;
-    return GP_EUNSUPPORTED;
+    if (!b || !psis || nsteps < 0) return set_error("bad argument"), GP_EINVAL;
+    for (int k = 0; k < b->count; ++k)
+        if (!psis[k]) return set_error("NULL problem grid"), GP_EINVAL;
+    if (nsteps == 0) return GP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    gp_status st = prepare(b, psis);
+    if (st != GP_OK) return st;
+    const int64_t step0 = b->plans[0]->step;
+    e = run_batch(b, step0, nsteps, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    for (gp_plan *p : b->plans) p->step += nsteps;
+    return check_error_flag(b, s);
 }
 
-gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream)
+gp_status gp_batch_observables(gp_batch *b, int k, const void *psi, gp_obs *out, void *stream)
 {
-    (void)batch; (void)k; (void)psi; (void)out; (void)stream;
-    return GP_EUNSUPPORTED;
+    if (!b || k < 0 || k >= b->count) return set_error("bad batch or index"), GP_EINVAL;
+    return gp_observables(b->plans[k], psi, out, stream);
 }
 
+gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
+{
+    if (!b) return set_error("bad batch"), GP_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const std::string key = cache_key(b);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream is(line);
+            std::string k2;
+            BatchConfig c;
+            c.spin_limit = b->cfg.spin_limit;
+            if (is >> k2 >> c.persistent >> c.lines >> c.ysegs >> c.grid && k2 == key) {
+                b->cfg = c;
+                return GP_OK;
+            }
+        }
+    }
+    // scratch copies of every problem (Gaussian-like content does not matter for timing)
+    std::vector<void *> scratch(b->count, nullptr);
+    for (int k = 0; k < b->count; ++k) {
+        const gp_plan *p = b->plans[k];
+        const size_t bytes = (size_t)p->npts * elem_bytes(b->prec);
+        e = hipMalloc(&scratch[k], bytes);
+        if (e == hipSuccess) e = hipMemsetAsync(scratch[k], 0, bytes, s);
+        if (e != hipSuccess) {
+            for (void *q : scratch) hipFree(q);
+            return hip_fail(e, "autotune scratch");
+        }
+    }
+    std::vector<BatchConfig> cands;
+    for (int lines : {1, 2, 4})
+        for (int ysegs : {1, 2, 4, 8}) {
+            BatchConfig c;
+            c.spin_limit = b->cfg.spin_limit;
+            c.persistent = 0;
+            c.lines = lines;
+            c.ysegs = ysegs;
+            cands.push_back(c);
+            if (b->mode == GP_REAL)
+                for (int grid : {256, 512, 1024, 2048}) {
+                    c.persistent = 1;
+                    c.grid = grid;
+                    cands.push_back(c);
+                }
+        }
+    const BatchConfig saved = b->cfg;
+    std::vector<int64_t> saved_steps;
+    for (gp_plan *p : b->plans) saved_steps.push_back(p->step);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    BatchConfig best_cfg = saved;
+    gp_status st = GP_OK;
+    const int64_t steps = 10;
+    for (const BatchConfig &c : cands) {
+        b->cfg = c;
+        st = prepare(b, scratch.data());
+        if (st != GP_OK) break;
+        if (run_batch(b, 0, 2, s) != hipSuccess) continue;  // warm-up
+        hipEventRecord(e0, s);
+        e = run_batch(b, 0, steps, s);
+        hipEventRecord(e1, s);
+        if (e != hipSuccess) continue;
+        hipEventSynchronize(e1);
+        if (check_error_flag(b, s) != GP_OK) continue;
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_cfg = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (void *q : scratch) hipFree(q);
+    for (int k = 0; k < b->count; ++k) b->plans[k]->step = saved_steps[k];
+    b->cfg = st == GP_OK ? best_cfg : saved;
+    b->bound.clear();  // rebuild for the caller's grids on the next step
+    if (st != GP_OK) return st;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key << " " << b->cfg.persistent << " " << b->cfg.lines << " " << b->cfg.ysegs << " " << b->cfg.grid
+          << "\n";
+    }
+    return GP_OK;
 }
+
+gp_status gp_batch_set_wait_limit(gp_batch *b, uint32_t polls)
+{
+    if (!b || polls < 1) return set_error("bad argument"), GP_EINVAL;
+    b->cfg.spin_limit = polls;
+    return GP_OK;
+}
+
+gp_status gp_batch_get_config(const gp_batch *b, int *persistent, int *lines, int *ysegs, int *grid)
+{
+    if (!b || !persistent || !lines || !ysegs || !grid) return set_error("bad argument"), GP_EINVAL;
+    *persistent = b->cfg.persistent;
+    *lines = b->cfg.lines;
+    *ysegs = b->cfg.ysegs;
+    *grid = b->cfg.grid;
+    return GP_OK;
+}
+
+gp_status gp_batch_set_config(gp_batch *b, int persistent, int lines, int ysegs, int grid)
+{
+    if (!b || persistent < 0 || persistent > 1 || lines < 1 || lines > 64 || ysegs < 1 || ysegs > 8 || grid < 1 ||
+        grid > 65536)
+        return set_error("bad argument"), GP_EINVAL;
+    if (persistent && b->mode != GP_REAL) return set_error("persistent batches run real time only"), GP_EUNSUPPORTED;
+    b->cfg.persistent = persistent;
+    b->cfg.lines = lines;
+    b->cfg.ysegs = ysegs;
+    b->cfg.grid = grid;
+    b->bound.clear();
+    return GP_OK;
+}
+
+}  // extern "C"

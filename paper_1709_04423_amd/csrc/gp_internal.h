@@ -61,6 +61,7 @@ struct SweepParams {
     double c_inf[2];      // c'_q (re, im)
     double b_inf[3];      // beta_q (re, im hi, im lo)
     const void *xmul;     // x scan multipliers: 12 rows x 64 lanes (forward steps 0..5, backward 0..5)
+    int xq;               // x scan points per lane (0: not the scan kernel)
     // potential substep on axis 0
     double dt, g;
     double hw2[3];        // 1/2 omega_a^2 of this step
@@ -71,6 +72,7 @@ struct SweepParams {
     const double *norm_total;  // F_RENORM: dV-less sum |psi|^2 of the previous step (one value)
     double dV;
     double *norm_out;     // F_NORM_OUT partials, one per workgroup
+    int64_t n_norm;       // partial slots per step parity (batched kernels offset by parity)
     double *adj_out;      // F_ADJ_N partials, two per workgroup
 };
 
@@ -147,6 +149,8 @@ double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
 // Sweep along one axis; flags per SweepFlags; adjoint selects the conjugate map.
 hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
                         int64_t step_index, const void *state, hipStream_t s);
+SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void *dst, bool adjoint,
+                              int64_t step_index, const void *state);
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
 hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
 // norm totals: one value per step parity, after the 2 x n_norm partials

@@ -157,10 +157,10 @@ template <typename R> struct LineCtx {
 };
 
 template <typename R, int FLAGS>
-__device__ __forceinline__ LineCtx<R> line_setup(const SweepParams &P, int lane)
+__device__ __forceinline__ LineCtx<R> line_setup(const SweepParams &P, int64_t group, int lane)
 {
     LineCtx<R> L;
-    const int64_t line = (int64_t)blockIdx.x * kLanes + lane;
+    const int64_t line = group * kLanes + lane;
     L.active = line < P.nlines;
     const int64_t l = L.active ? line : 0;
     L.base = (l % P.m1) * P.s1 + (l / P.m1) * P.s2;
@@ -242,11 +242,11 @@ __device__ __forceinline__ cp<R> potential_adjoint(cp<R> lam, int64_t t, const V
     return {lam.re * c - lam.im * s + k2 * psi.re, lam.re * s + lam.im * c + k2 * psi.im};
 }
 
+// Wavefront sums of the epilogue accumulators, written to partial slot g.
 template <typename R, int FLAGS>
 __device__ __forceinline__ void write_partials(const SweepParams &P, int lane, double nacc,
-                                               double acc_w, double acc_g)
+                                               double acc_w, double acc_g, int64_t g)
 {
-    const int64_t g = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;  // one partial per workgroup and segment
     if (FLAGS & F_NORM_OUT) {
         nacc = wave_sum(nacc);
         if (lane == 0) P.norm_out[g] = nacc;

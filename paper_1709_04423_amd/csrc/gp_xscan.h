@@ -1,0 +1,184 @@
+// x sweep (contiguous axis): one wavefront per grid line, shared by the x kernel
+// and the batched kernels.
+//
+// Each lane holds Q = n/64 (rounded up to a power of two) consecutive points
+// of the line, so every load and store of a wavefront is one contiguous
+// segment, and many lines per CU are in flight at once (no LDS, modest
+// registers).  The two Thomas recurrences of the scaled CN system are first-
+// order affine recurrences along the line,
+//     forward   y_p = -c'_p y_{p-1} + c'_p rhs_p,
+//     backward  u'_p = -c'_p u'_{p+1} + y_p,
+// so each lane composes the affine maps of its Q points into one map, the
+// lanes combine their maps with a Hillis-Steele scan over shuffles, and each
+// lane then applies its incoming carry to its own points.  A scan of S steps
+// lets a carry travel Q 2^S points; the influence of points further away is
+// multiplied by prod |c'| <= rho^(Q 2^S), and the host picks S as the smallest
+// with Q 2^S > K (the same bound as the windowed solver) -- S = 6 is the full
+// scan and exact.  The potential substep is applied to the loaded values, and
+// the norm / adjoint epilogues to the stored ones, as in the other sweeps.
+#pragma once
+
+#include "gp_sweep_common.h"
+
+namespace gp {
+
+constexpr int kXWaves = kXWavesPerGroup;  // lines (wavefronts) per workgroup
+
+template <typename R> __device__ __forceinline__ cp<R> cmul(cp<R> a, cp<R> b)
+{
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+template <typename R> __device__ __forceinline__ cp<R> cfma(cp<R> a, cp<R> b, cp<R> c)  // a*b + c
+{
+    return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+template <typename R> __device__ __forceinline__ cp<R> shfl_up_c(cp<R> v, int d)
+{
+    return {__shfl_up(v.re, d, kLanes), __shfl_up(v.im, d, kLanes)};
+}
+template <typename R> __device__ __forceinline__ cp<R> shfl_down_c(cp<R> v, int d)
+{
+    return {__shfl_down(v.re, d, kLanes), __shfl_down(v.im, d, kLanes)};
+}
+
+// Table row of point q: (c', beta, beta_lo); constant past q_const, zero past n.
+template <typename R, typename V>
+__device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict__ tab, int64_t q, V &c, V &b,
+                                       V &blo)
+{
+    if (q >= P.n) {
+        c.x = c.y = b.x = b.y = blo.x = blo.y = R(0);
+    } else if (q >= P.q_const) {
+        c.x = R(P.c_inf[0]);
+        c.y = R(P.c_inf[1]);
+        b.x = R(P.b_inf[0]);
+        b.y = R(P.b_inf[1]);
+        blo.x = R(P.b_inf[2]);
+        blo.y = R(0);
+    } else {
+        c = tab[3 * (q + 1)];
+        b = tab[3 * (q + 1) + 1];
+        blo = tab[3 * (q + 1) + 2];
+    }
+}
+
+// Each wavefront solves kXLines lines in turn.  Everything that depends only
+// on the position along the line is computed once: the table rows of the
+// lane's points are loaded before the line loop, and the multiplier halves of
+// the lane's composed maps at every scan step come precomputed from the host
+// (their products involve only the table), so per line only the data halves
+// (the F and G of the affine maps) are composed and scanned.
+constexpr int kXLines = kXLinesPerGroup / kXWavesPerGroup;
+
+// One wavefront solves lines first .. first+count-1 (those below P.nlines),
+// adding its epilogue sums to nacc / acc_w / acc_g.
+template <typename R, int MODE, int FLAGS, int Q>
+__device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
+                                            typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
+                                            const typename CT<R>::V *__restrict__ state, int64_t first, int count,
+                                            double &nacc, double &acc_w, double &acc_g)
+{
+    using V = typename CT<R>::V;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int64_t n = P.n;
+    const int64_t q0 = (int64_t)lane * Q;
+    const int S = P.scan_steps;
+    const cp<R> zero = {R(0), R(0)};
+
+    // multipliers of this lane's composed maps before each scan step (host table:
+    // rows s = 0..5 forward, 6..11 backward, one value per lane)
+    const V *__restrict__ xmul = (const V *)P.xmul;
+    const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
+    V nxt[Q];  // the next line's values, loaded while the current one is solved
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        nxt[i] = (first < P.nlines && q0 + i < n) ? src[first * n + q0 + i] : to_v<V>(zero);
+#pragma unroll 1
+    for (int li = 0; li < count; ++li) {
+        const int64_t line = first + li;
+        if (line >= P.nlines) break;  // uniform across the wavefront
+        const int64_t base = line * n;
+        LineCtx<R> L = line_ctx_of<R>(P, line);
+        if (FLAGS & F_RENORM) L.scale = renorm;
+
+        cp<R> u[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) u[i] = from_v<R>(nxt[i]);
+        if (li + 1 < count) {
+            const int64_t nl = line + 1;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                nxt[i] = (nl < P.nlines && q0 + i < n) ? src[nl * n + q0 + i] : to_v<V>(zero);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t q = q0 + i;
+            if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
+        }
+        cp<R> left = shfl_up_c(u[Q - 1], 1);
+        cp<R> right = shfl_down_c(u[0], 1);
+        if (lane == 0) left = zero;
+        if (lane == kLanes - 1) right = zero;
+
+        // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
+        // table rows: kernel-argument constants except on the first few lanes
+        cp<R> f[Q], ac[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const cp<R> um1 = i == 0 ? left : u[i - 1];
+            const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
+            V c, b, blo;
+            row_of<R>(P, tab, q0 + i, c, b, blo);
+            const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
+            f[i] = cmul(from_v<R>(c), rhs);
+            ac[i] = {-c.x, -c.y};
+        }
+        cp<R> F = f[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) F = cfma(ac[i], F, f[i]);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s < S) {  // uniform
+                const cp<R> Fp = shfl_up_c(F, 1 << s);
+                if (lane >= (1 << s)) F = cfma(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
+            }
+        }
+        cp<R> y = shfl_up_c(F, 1);
+        if (lane == 0) y = zero;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            y = cfma(ac[i], y, f[i]);
+            f[i] = y;
+        }
+        // backward: u'_p = a_p u'_{p+1} + y_p
+        cp<R> G = f[Q - 1];
+#pragma unroll
+        for (int i = Q - 2; i >= 0; --i) G = cfma(ac[i], G, f[i]);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            if (s < S) {  // uniform
+                const cp<R> Gp = shfl_down_c(G, 1 << s);
+                if (lane + (1 << s) < kLanes) G = cfma(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
+            }
+        }
+        cp<R> v = shfl_down_c(G, 1);
+        if (lane == kLanes - 1) v = zero;
+#pragma unroll
+        for (int i = Q - 1; i >= 0; --i) {
+            v = cfma(ac[i], v, f[i]);
+            u[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t q = q0 + i;
+            if (q < n) {
+                cp<R> w = u[i];
+                if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
+                if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, q, state, base + q, P, L, acc_w, acc_g);
+                dst[base + q] = to_v<V>(w);
+            }
+        }
+    }
+}
+
+}  // namespace gp
