@@ -189,6 +189,40 @@ def test_observables_of_gaussian_closed_forms():
     assert abs(o["energy"] - (o["ekin"] + o["epot"] + o["eint"])) < 1e-13
 
 
+def test_observable_sums_are_correctly_rounded_sums():
+    # the observables are plain rectangle sums; on a 10^6-point grid the oracle
+    # must return them to within a few ulps of math.fsum (correctly rounded) of
+    # the same per-point terms, so its own summation error stays far below the
+    # 1e-12 GPU parity bar (a bare running sum drifts by ~1e-13..1e-12 here)
+    from math import fsum
+    # Thomas-Fermi profile sqrt(max(mu - V, 0) / g) plus seeded noise: a plateau
+    # of nearly equal terms, where rounding errors of a running sum add up
+    n, dx, omega, g = (128, 96, 80), (0.1, 0.12, 0.15), (1.0, 1.3, 0.8), 250.0
+    xs = [np.arange(n[a]) * dx[a] - 0.5 * n[a] * dx[a] for a in range(3)]
+    V = (0.5 * omega[0] * omega[0] * xs[0] * xs[0])[None, None, :] \
+        + (0.5 * omega[1] * omega[1] * xs[1] * xs[1])[None, :, None]
+    V = V + (0.5 * omega[2] * omega[2] * xs[2] * xs[2])[:, None, None]
+    tf = np.sqrt(np.maximum(4.0 - V, 0.0) / g)
+    psi = tf / np.sqrt(dx[0] * dx[1] * dx[2] * np.sum(tf * tf)) + 1e-6 * inputs.random_field(tf.shape, 77)
+    o = oracle.observables(psi, dx, omega, g)
+    d = psi.real * psi.real + psi.imag * psi.imag
+    dv = dx[0] * dx[1] * dx[2]
+    norm = dv * fsum(d.ravel())
+    epot = dv * fsum((V * d).ravel())
+    eint = 0.5 * g * dv * fsum((d * d).ravel())
+    ekin = 0.0
+    for a in range(3):
+        ax = 2 - a
+        pad = [(0, 0)] * 3
+        pad[ax] = (1, 1)
+        diff = np.diff(np.pad(psi, pad), axis=ax)
+        ekin += 0.5 * dv * fsum((diff.real * diff.real + diff.imag * diff.imag).ravel()) / (dx[a] * dx[a])
+    ref = {"norm": norm, "epot": epot, "eint": eint, "ekin": ekin, "energy": ekin + epot + eint,
+           "mu": ekin + epot + 2 * eint}
+    for k, v in ref.items():
+        assert abs(o[k] - v) <= 4e-15 * abs(v), (k, o[k], v)
+
+
 def test_kinetic_energy_random_field_2d():
     shape, dx = (13, 17), (0.3, 0.2)
     psi = inputs.random_field(shape, 11)
