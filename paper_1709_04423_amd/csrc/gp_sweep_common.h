@@ -91,45 +91,68 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Phase factors of the potential substep.  Its angle is small in practice
-// (|theta| = dt (V + g|psi|^2) ~ 0.06 on the 256^3 workload), so for
-// |theta| <= 1/8 the Taylor series of sin, cos and exp are evaluated in Horner
-// form with coefficients (-1)^k/(2k+1)!, (-1)^k/(2k)! and 1/k! -- through
-// theta^11, theta^10 and theta^11 in FP64 (first omitted term below 3e-20
-// relative) and theta^7, theta^6, theta^6 in FP32 -- and larger angles take the
-// library functions.
+// Phase factors of the potential substep.  Real time multiplies by
+// e^{-i theta} = 1 - h - i s with s = sin(theta) and h = 1 - cos(theta) =
+// 2 sin^2(theta/2), applied as u + (s-term - h u): h is computed to full
+// relative precision instead of rounding cos(theta) next to 1, so |1 - h - i s|
+// differs from 1 by about eps h, not eps.  Near the Thomas-Fermi plateau theta
+// is almost the same at every point, and a rounded cos(theta) would then scale
+// the norm by the same factor every step (an FP32 drift of order 1e-5 per
+// 1000 steps).  The angle is small in practice (|theta| = dt (V + g|psi|^2)
+// ~ 0.06 on the 256^3 workload), so for |theta| <= 1/8 the Taylor series are
+// evaluated in Horner form with coefficients (-1)^k/(2k+1)! for sin,
+// (-1)^(k+1)/(2k)! for h and 1/k! for exp -- through theta^11, theta^10 and
+// theta^11 in FP64 (first omitted term below 4e-18 relative) and theta^7,
+// theta^6, theta^6 in FP32 (below 2e-10) -- and larger angles use the library
+// sin and cos of theta/2.
 template <typename R> struct Taylor {
     static constexpr R s3 = R(-1.0 / 6.0), s5 = R(1.0 / 120.0), s7 = R(-1.0 / 5040.0),
                        s9 = R(1.0 / 362880.0), s11 = R(-1.0 / 39916800.0);
-    static constexpr R c2 = R(-1.0 / 2.0), c4 = R(1.0 / 24.0), c6 = R(-1.0 / 720.0),
-                       c8 = R(1.0 / 40320.0), c10 = R(-1.0 / 3628800.0);
+    static constexpr R h2 = R(1.0 / 2.0), h4 = R(-1.0 / 24.0), h6 = R(1.0 / 720.0),
+                       h8 = R(-1.0 / 40320.0), h10 = R(1.0 / 3628800.0);
     static constexpr R e2 = R(1.0 / 2.0), e3 = R(1.0 / 6.0), e4 = R(1.0 / 24.0), e5 = R(1.0 / 120.0),
                        e6 = R(1.0 / 720.0), e7 = R(1.0 / 5040.0), e8 = R(1.0 / 40320.0),
                        e9 = R(1.0 / 362880.0), e10 = R(1.0 / 3628800.0), e11 = R(1.0 / 39916800.0);
 };
 
-__device__ __forceinline__ void sincos_r(double t, double *s, double *c)
+// s = sin(t), h = 1 - cos(t)
+__device__ __forceinline__ void phase_r(double t, double *s, double *h)
 {
     using T = Taylor<double>;
     if (fabs(t) <= 0.125) {
         const double t2 = t * t;
         *s = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * (T::s7 + t2 * (T::s9 + t2 * T::s11))));
-        *c = 1.0 + t2 * (T::c2 + t2 * (T::c4 + t2 * (T::c6 + t2 * (T::c8 + t2 * T::c10))));
+        *h = t2 * (T::h2 + t2 * (T::h4 + t2 * (T::h6 + t2 * (T::h8 + t2 * T::h10))));
     } else {
-        sincos(t, s, c);
+        double sh, ch;
+        sincos(0.5 * t, &sh, &ch);
+        *s = 2.0 * sh * ch;
+        *h = 2.0 * sh * sh;
     }
 }
-__device__ __forceinline__ void sincos_r(float t, float *s, float *c)
+__device__ __forceinline__ void phase_r(float t, float *s, float *h)
 {
     using T = Taylor<float>;
     if (fabsf(t) <= 0.125f) {
         const float t2 = t * t;
         *s = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * T::s7));
-        *c = 1.0f + t2 * (T::c2 + t2 * (T::c4 + t2 * T::c6));
+        *h = t2 * (T::h2 + t2 * (T::h4 + t2 * T::h6));
     } else {
-        sincosf(t, s, c);
+        float sh, ch;
+        sincosf(0.5f * t, &sh, &ch);
+        *s = 2.0f * sh * ch;
+        *h = 2.0f * sh * sh;
     }
 }
+
+// u e^{-i sg t} for sg = +1 / -1 given s = sin t, h = 1 - cos t
+template <typename R>
+__device__ __forceinline__ cp<R> rotate(cp<R> u, R s, R h, R sg)
+{
+    const R ss = sg * s;
+    return {u.re + (ss * u.im - h * u.re), u.im - (ss * u.re + h * u.im)};
+}
+
 __device__ __forceinline__ double exp_r(double t)
 {
     using T = Taylor<double>;
@@ -210,9 +233,9 @@ __device__ __forceinline__ cp<R> potential_substep(cp<R> u, int64_t q, const Swe
     const R x = R(((double)q + P.x0[0]) * P.dx[0]);
     const R theta = R(P.dt) * (L.vperp + L.hw0 * x * x + R(P.g) * (u.re * u.re + u.im * u.im));
     if (MODE == GP_REAL) {
-        R s, c;
-        sincos_r(theta, &s, &c);
-        return {u.re * c + u.im * s, u.im * c - u.re * s};
+        R s, h;
+        phase_r(theta, &s, &h);
+        return rotate(u, s, h, R(1));
     }
     const R f = exp_r(-theta);
     return {u.re * f, u.im * f};
@@ -230,16 +253,16 @@ __device__ __forceinline__ cp<R> potential_adjoint(cp<R> lam, int64_t t, const V
     const R x = R(((double)t + P.x0[0]) * P.dx[0]);
     const R d = psi.re * psi.re + psi.im * psi.im;
     const R theta = R(P.dt) * (L.vperp + L.hw0 * x * x + R(P.g) * d);
-    R s, c;
-    sincos_r(theta, &s, &c);
-    const R ur = psi.re * c + psi.im * s;  // u = psi e^{-i theta}
-    const R ui = psi.im * c - psi.re * s;
-    const R w = lam.re * ui - lam.im * ur;  // Im(conj(lam) u)
+    R s, h;
+    phase_r(theta, &s, &h);
+    const cp<R> u = rotate(psi, s, h, R(1));  // u = psi e^{-i theta}
+    const R w = lam.re * u.im - lam.im * u.re;  // Im(conj(lam) u)
     const R k2 = R(2) * R(P.dt) * R(P.g) * w;
     const R xs2 = P.sched_axis == 0 ? x * x : (P.sched_axis == 1 ? L.ysq : L.zsq);
     acc_w += (double)w * (double)xs2;
     acc_g += (double)w * (double)d;
-    return {lam.re * c - lam.im * s + k2 * psi.re, lam.re * s + lam.im * c + k2 * psi.im};
+    const cp<R> l = rotate(lam, s, h, R(-1));  // lam e^{+i theta}
+    return {l.re + k2 * psi.re, l.im + k2 * psi.im};
 }
 
 // Wavefront sums of the epilogue accumulators, written to partial slot g.
