@@ -90,8 +90,9 @@ static __device__ __forceinline__ int wave_first_lane_i(int v) { return __builti
 // QMAX: the largest points-per-lane of the batch's x lines; only the solver
 // variants up to it are compiled into a kernel (their registers would be
 // allocated even when not taken).
+// lds: the wavefront's LDS region (at least x_lds_bytes<R>(QMAX) bytes).
 template <typename R, int MODE, int FLAGS, int QMAX>
-__device__ __forceinline__ void run_x_item(const SweepParams &P0, const BatchItem &it, int64_t step)
+__device__ __forceinline__ void run_x_item(const SweepParams &P0, const BatchItem &it, int64_t step, char *lds)
 {
     using V = typename CT<R>::V;
     SweepParams P = P0;
@@ -100,14 +101,16 @@ __device__ __forceinline__ void run_x_item(const SweepParams &P0, const BatchIte
     const V *src = (const V *)P.psi;
     V *dst = (V *)P.out;
     const V *tab = (const V *)P.tab;
-    if (P.xq == 1) x_scan_wave<R, MODE, FLAGS, 1>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
-    else if (P.xq == 2) x_scan_wave<R, MODE, FLAGS, 2>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+    V *xl = (V *)lds;
+    if (P.xq == 1) x_scan_wave<R, MODE, FLAGS, 1>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
+    else if (P.xq == 2) x_scan_wave<R, MODE, FLAGS, 2>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
     else if constexpr (QMAX >= 4) {
-        if (P.xq == 4) x_scan_wave<R, MODE, FLAGS, 4>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+        if (P.xq == 4) x_scan_wave<R, MODE, FLAGS, 4>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
         else if constexpr (QMAX >= 8) {
-            if (P.xq == 8) x_scan_wave<R, MODE, FLAGS, 8>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+            if (P.xq == 8) x_scan_wave<R, MODE, FLAGS, 8>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
             else if constexpr (QMAX >= 16) {
-                if (P.xq == 16) x_scan_wave<R, MODE, FLAGS, 16>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c);
+                if (P.xq == 16)
+                    x_scan_wave<R, MODE, FLAGS, 16>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
             }
         }
     }
@@ -144,13 +147,15 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_x(const SweepPara
                                                                   const BatchItem *__restrict__ items, int64_t nitems,
                                                                   int64_t step, int renorm)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBatchWaves + wave_first_lane_i(threadIdx.x / kLanes);
+    __shared__ typename CT<R>::V xl[kBatchWaves][kLanes * (QMAX + 1)];
+    const int w = wave_first_lane_i(threadIdx.x / kLanes);
+    const int64_t i = (int64_t)blockIdx.x * kBatchWaves + w;
     if (i >= nitems) return;  // whole wavefront
     const BatchItem it = items[i];
     if (MODE == GP_IMAG && renorm)
-        run_x_item<R, MODE, F_FUSE_N | F_RENORM, QMAX>(px[it.prob], it, step);
+        run_x_item<R, MODE, F_FUSE_N | F_RENORM, QMAX>(px[it.prob], it, step, (char *)xl[w]);
     else
-        run_x_item<R, MODE, F_FUSE_N, QMAX>(px[it.prob], it, step);
+        run_x_item<R, MODE, F_FUSE_N, QMAX>(px[it.prob], it, step, (char *)xl[w]);
 }
 
 template <typename R, int MODE>
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
             int *ydone = xdone + 1;
             // the previous step's y items of this problem are done
             if (!wait_at_least(ydone + 2 * it.prob, (int)(sl * ny_per[it.prob]), error, limit)) break;
-            run_x_item<R, GP_REAL, F_FUSE_N, QMAX>(px[it.prob], it, step0 + sl);
+            run_x_item<R, GP_REAL, F_FUSE_N, QMAX>(px[it.prob], it, step0 + sl, lds);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if ((threadIdx.x & (kLanes - 1)) == 0)
                 __hip_atomic_fetch_add(xdone + 2 * it.prob, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -356,6 +361,9 @@ static gp_status prepare(gp_batch *b, void *const *psis)
         nparts[k] = groups * segs;
         lds_wave = std::max(lds_wave, b->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(p->ax[1].L)
                                                          : window_lds_bytes<float, kStrided, 4>(p->ax[1].L));
+        // the persistent kernel's x items use the same region for their transposes
+        lds_wave = std::max(lds_wave, b->prec == GP_C128 ? x_lds_bytes<double>(p->ax[0].xq)
+                                                         : x_lds_bytes<float>(p->ax[0].xq));
     }
     gp_status st = upload((void **)&b->d_px, px.data(), px.size() * sizeof(SweepParams));
     if (st == GP_OK) st = upload((void **)&b->d_py, py.data(), py.size() * sizeof(SweepParams));

@@ -1,11 +1,17 @@
 // x sweep (contiguous axis): one wavefront per grid line, shared by the x kernel
 // and the batched kernels.
 //
-// Each lane holds Q = n/64 (rounded up to a power of two) consecutive points
-// of the line, so every load and store of a wavefront is one contiguous
-// segment, and many lines per CU are in flight at once (no LDS, modest
-// registers).  The two Thomas recurrences of the scaled CN system are first-
-// order affine recurrences along the line,
+// Each lane solves Q = n/64 (rounded up to a power of two) consecutive points
+// of the line.  Global loads and stores are coalesced instead (lane L moves
+// points L + 64 i, so each instruction covers one contiguous 1 KB / 512 B row
+// of the line), and a per-wavefront LDS buffer transposes between the two
+// layouts; lane-strided global access would touch four times as many cache
+// lines per instruction and caps streaming well below the coalesced rate.  The
+// buffer holds 64 (Q + 1) values with one pad slot after every Q, which keeps
+// both access patterns free of bank conflicts.
+//
+// The two Thomas recurrences of the scaled CN system are first-order affine
+// recurrences along the line,
 //     forward   y_p = -c'_p y_{p-1} + c'_p rhs_p,
 //     backward  u'_p = -c'_p u'_{p+1} + y_p,
 // so each lane composes the affine maps of its Q points into one map, the
@@ -15,7 +21,8 @@
 // multiplied by prod |c'| <= rho^(Q 2^S), and the host picks S as the smallest
 // with Q 2^S > K (the same bound as the windowed solver) -- S = 6 is the full
 // scan and exact.  The potential substep is applied to the loaded values, and
-// the norm / adjoint epilogues to the stored ones, as in the other sweeps.
+// the norm / adjoint epilogues to the stored ones (both in the coalesced
+// layout), as in the other sweeps.
 #pragma once
 
 #include "gp_sweep_common.h"
@@ -24,6 +31,20 @@ namespace gp {
 
 constexpr int kXWaves = kXWavesPerGroup;  // lines (wavefronts) per workgroup
 
+// Bytes of one wavefront's transpose buffer for Q points per lane.
+template <typename R> __host__ __device__ constexpr size_t x_lds_bytes(int Q)
+{
+    return (size_t)kLanes * (Q + 1) * sizeof(typename CT<R>::V);
+}
+
+// Orders one wavefront's LDS accesses (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R> __device__ __forceinline__ cp<R> cmul(cp<R> a, cp<R> b)
 {
     return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
@@ -31,6 +52,19 @@ template <typename R> __device__ __forceinline__ cp<R> cmul(cp<R> a, cp<R> b)
 template <typename R> __device__ __forceinline__ cp<R> cfma(cp<R> a, cp<R> b, cp<R> c)  // a*b + c
 {
     return {fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+// Products with a CN coefficient or scan multiplier k.  In imaginary time
+// every coefficient is real (c', beta and their products), so only k.re is
+// used there: half the registers and arithmetic of a complex product.
+template <int MODE, typename R> __device__ __forceinline__ cp<R> kmul(cp<R> k, cp<R> v)
+{
+    if (MODE == GP_IMAG) return {k.re * v.re, k.re * v.im};
+    return cmul(k, v);
+}
+template <int MODE, typename R> __device__ __forceinline__ cp<R> kfma(cp<R> k, cp<R> v, cp<R> w)  // k*v + w
+{
+    if (MODE == GP_IMAG) return {fma(k.re, v.re, w.re), fma(k.re, v.im, w.im)};
+    return cfma(k, v, w);
 }
 template <typename R> __device__ __forceinline__ cp<R> shfl_up_c(cp<R> v, int d)
 {
@@ -72,16 +106,18 @@ constexpr int kXLines = kXLinesPerGroup / kXWavesPerGroup;
 
 // One wavefront solves lines first .. first+count-1 (those below P.nlines),
 // adding its epilogue sums to nacc / acc_w / acc_g.
+// xl: this wavefront's LDS buffer of x_lds_bytes<R>(Q) bytes.
 template <typename R, int MODE, int FLAGS, int Q>
 __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
                                             typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
                                             const typename CT<R>::V *__restrict__ state, int64_t first, int count,
-                                            double &nacc, double &acc_w, double &acc_g)
+                                            double &nacc, double &acc_w, double &acc_g, typename CT<R>::V *xl)
 {
     using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int64_t n = P.n;
     const int64_t q0 = (int64_t)lane * Q;
+    auto pad = [](int q) { return q + q / Q; };  // slot of point q in xl
     const int S = P.scan_steps;
     const cp<R> zero = {R(0), R(0)};
 
@@ -92,7 +128,7 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     V nxt[Q];  // the next line's values, loaded while the current one is solved
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        nxt[i] = (first < P.nlines && q0 + i < n) ? src[first * n + q0 + i] : to_v<V>(zero);
+        nxt[i] = (first < P.nlines && lane + kLanes * i < n) ? src[first * n + lane + kLanes * i] : to_v<V>(zero);
 #pragma unroll 1
     for (int li = 0; li < count; ++li) {
         const int64_t line = first + li;
@@ -108,12 +144,19 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
             const int64_t nl = line + 1;
 #pragma unroll
             for (int i = 0; i < Q; ++i)
-                nxt[i] = (nl < P.nlines && q0 + i < n) ? src[nl * n + q0 + i] : to_v<V>(zero);
+                nxt[i] = (nl < P.nlines && lane + kLanes * i < n) ? src[nl * n + lane + kLanes * i] : to_v<V>(zero);
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t q = q0 + i;
+            const int64_t q = lane + kLanes * i;
             if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
+        }
+        if (Q > 1) {  // coalesced -> Q consecutive points per lane
+#pragma unroll
+            for (int i = 0; i < Q; ++i) xl[pad(lane + kLanes * i)] = to_v<V>(u[i]);
+            wave_lds_sync();
+#pragma unroll
+            for (int i = 0; i < Q; ++i) u[i] = from_v<R>(xl[pad(lane * Q + i)]);
         }
         cp<R> left = shfl_up_c(u[Q - 1], 1);
         cp<R> right = shfl_down_c(u[0], 1);
@@ -130,47 +173,55 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
             V c, b, blo;
             row_of<R>(P, tab, q0 + i, c, b, blo);
             const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
-            f[i] = cmul(from_v<R>(c), rhs);
-            ac[i] = {-c.x, -c.y};
+            f[i] = kmul<MODE>(from_v<R>(c), rhs);
+            ac[i] = {-c.x, MODE == GP_IMAG ? R(0) : -c.y};
         }
         cp<R> F = f[0];
 #pragma unroll
-        for (int i = 1; i < Q; ++i) F = cfma(ac[i], F, f[i]);
+        for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac[i], F, f[i]);
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
             if (s < S) {  // uniform
                 const cp<R> Fp = shfl_up_c(F, 1 << s);
-                if (lane >= (1 << s)) F = cfma(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
+                if (lane >= (1 << s)) F = kfma<MODE>(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
             }
         }
         cp<R> y = shfl_up_c(F, 1);
         if (lane == 0) y = zero;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            y = cfma(ac[i], y, f[i]);
+            y = kfma<MODE>(ac[i], y, f[i]);
             f[i] = y;
         }
         // backward: u'_p = a_p u'_{p+1} + y_p
         cp<R> G = f[Q - 1];
 #pragma unroll
-        for (int i = Q - 2; i >= 0; --i) G = cfma(ac[i], G, f[i]);
+        for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac[i], G, f[i]);
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
             if (s < S) {  // uniform
                 const cp<R> Gp = shfl_down_c(G, 1 << s);
-                if (lane + (1 << s) < kLanes) G = cfma(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
+                if (lane + (1 << s) < kLanes) G = kfma<MODE>(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
             }
         }
         cp<R> v = shfl_down_c(G, 1);
         if (lane == kLanes - 1) v = zero;
 #pragma unroll
         for (int i = Q - 1; i >= 0; --i) {
-            v = cfma(ac[i], v, f[i]);
+            v = kfma<MODE>(ac[i], v, f[i]);
             u[i] = v;
+        }
+        if (Q > 1) {  // back to the coalesced layout
+#pragma unroll
+            for (int i = 0; i < Q; ++i) xl[pad(lane * Q + i)] = to_v<V>(u[i]);
+            wave_lds_sync();
+#pragma unroll
+            for (int i = 0; i < Q; ++i) u[i] = from_v<R>(xl[pad(lane + kLanes * i)]);
+            wave_lds_sync();
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t q = q0 + i;
+            const int64_t q = lane + kLanes * i;
             if (q < n) {
                 cp<R> w = u[i];
                 if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;

@@ -13,9 +13,10 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
 {
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
+    __shared__ typename CT<R>::V xl[kXWaves][kLanes * (Q + 1)];
     double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
     x_scan_wave<R, MODE, FLAGS, Q>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * kXLines,
-                                   kXLines, nacc, acc_w, acc_g);
+                                   kXLines, nacc, acc_w, acc_g, xl[wave]);
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
         __shared__ double red[kXWaves][3];
         nacc = wave_sum(nacc);
