@@ -90,6 +90,7 @@ typedef struct {
     double window_bound[3]; /* rho^(K+1): bound on the window's relative truncation */
     int64_t step;         /* index of the next step (selects the trap schedule) */
     int64_t device_bytes; /* device memory owned by the plan */
+    int xy_fused;         /* 3D: row segments per plane of the fused x+y sweep, 0 = separate sweeps */
 } gp_plan_info;
 
 typedef struct gp_plan gp_plan;
@@ -122,6 +123,15 @@ gp_status gp_observables(gp_plan *plan, const void *psi, gp_obs *out, void *stre
 /* Set / get the index of the next step (resume, recompute segments). */
 gp_status gp_plan_set_step(gp_plan *plan, int64_t step);
 gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info);
+
+/* 3D forward steps: enable (1, the default) or disable (0) the fused x+y sweep.
+ * The x and y Crank-Nicolson substeps of the step (program summary, "Solution
+ * method") act plane by plane, so where the plan's shape allows (x extent 128,
+ * 192 or 256, and a y window of 2..4 blocks that fits in LDS) one kernel reads
+ * each xy-plane once and writes the result of both substeps; otherwise, or
+ * when disabled, the sweeps run as separate kernels.  Both give the same step
+ * up to rounding.  GP_EINVAL for a NULL plan or a flag other than 0 or 1. */
+gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable);
 
 /* Host-only (no GPU needed): one axis's Thomas table exactly as a plan stores
  * it, for checking.  The CN substep along an axis of n points is solved in the
@@ -214,7 +224,7 @@ gp_status gp_plan_timing_enable(gp_plan *plan, int64_t capacity);
 /* Synchronise the events and report, per kernel kind (names in
  * gp_kernel_name(kind), kind = 0..GP_NUM_KERNEL_KINDS-1), the number of
  * recorded launches and their total duration in milliseconds; clears the log. */
-#define GP_NUM_KERNEL_KINDS 13
+#define GP_NUM_KERNEL_KINDS 14
 gp_status gp_plan_timing_read(gp_plan *plan, int64_t *counts, double *total_ms);
 const char *gp_kernel_name(int kind);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgp.so")
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED, GP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GP_IMAG, GP_REAL = 0, 1
 GP_C128, GP_C64 = 0, 1
-GP_NUM_KERNEL_KINDS = 13
+GP_NUM_KERNEL_KINDS = 14
 
 c_i64p = ctypes.POINTER(ctypes.c_int64)
 c_dp = ctypes.POINTER(ctypes.c_double)
@@ -42,7 +42,7 @@ class GpObs(ctypes.Structure):
 class GpPlanInfo(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("window", ctypes.c_int * 3),
                 ("rho", ctypes.c_double * 3), ("window_bound", ctypes.c_double * 3),
-                ("step", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("step", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("xy_fused", ctypes.c_int)]
 
 
 class GpError(RuntimeError):
@@ -71,6 +71,7 @@ def lib():
             "gp_observables": [vp, vp, ctypes.POINTER(GpObs), vp],
             "gp_plan_set_step": [vp, i64],
             "gp_plan_get_info": [vp, ctypes.POINTER(GpPlanInfo)],
+            "gp_plan_set_xy_fusion": [vp, i32],
             "gp_thomas_table": [i64, d, d, i32, i32, i32, c_dp, c_dp, ctypes.POINTER(ctypes.c_int), c_dp],
             "gp_step_adjoint": [vp, vp, vp, i64, i64, vp, vp, vp],
             "gp_batch_create": [pp, i32, c_i64p, c_dp, c_dp, i32, c_dp, c_dp, i32],
@@ -210,7 +211,12 @@ class Plan:
         i = GpPlanInfo()
         check(lib().gp_plan_get_info(self._h, ctypes.byref(i)), "gp_plan_get_info")
         return {"ndim": i.ndim, "n": tuple(i.n), "window": tuple(i.window), "rho": tuple(i.rho),
-                "window_bound": tuple(i.window_bound), "step": i.step, "device_bytes": i.device_bytes}
+                "window_bound": tuple(i.window_bound), "step": i.step, "device_bytes": i.device_bytes,
+                "xy_fused": i.xy_fused}
+
+    def set_xy_fusion(self, enable: bool):
+        """3D: use (True, the default) or skip the fused x+y sweep where the shape allows it."""
+        check(lib().gp_plan_set_xy_fusion(self._h, int(bool(enable))), "gp_plan_set_xy_fusion")
 
     def adjoint(self, states, lam, n_first: int, nsteps: int, dsched=None, dg=None, stream=None):
         """Reverse nsteps real-time steps (see gp_step_adjoint)."""

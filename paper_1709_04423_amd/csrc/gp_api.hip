@@ -339,7 +339,8 @@ const char *gp_kernel_name(int kind)
 {
     static const char *names[GP_NUM_KERNEL_KINDS] = {
         "sweep_x", "sweep_y", "sweep_z", "sweep_exact", "scale", "observables",
-        "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy", "norm_final"};
+        "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy", "norm_final",
+        "sweep_xy"};
     if (kind < 0 || kind >= GP_NUM_KERNEL_KINDS) return "unknown";
     return names[kind];
 }
@@ -463,6 +464,12 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         free_plan(p);
         return st;
     }
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
+        max_lds = 0;
+    p->xy_segs = xy_choose_segments(p, max_lds);
+    // complex64 runs its separate sweeps at higher occupancy, as fast as fused
+    p->xy_enabled = prec == GP_C128;
     *out = p;
     return GP_OK;
 }
@@ -495,6 +502,14 @@ gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info)
     }
     info->step = plan->step;
     info->device_bytes = plan->device_bytes;
+    info->xy_fused = plan->xy_enabled ? plan->xy_segs : 0;
+    return GP_OK;
+}
+
+gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable)
+{
+    if (!plan || (enable != 0 && enable != 1)) return set_error("bad plan or flag"), GP_EINVAL;
+    plan->xy_enabled = enable != 0;
     return GP_OK;
 }
 
@@ -544,9 +559,14 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const bool imag = p->mode == GP_IMAG;
+    const bool fused = p->ndim == 3 && p->xy_segs > 0 && p->xy_enabled;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n = p->step + k;
-        for (int a = 0; a < p->ndim; ++a) {
+        if (fused) {  // x and y in one pass psi -> work, then z work -> psi
+            e = launch_xy(p, psi, p->d_work, F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0), n, s);
+            if (e != hipSuccess) return hip_fail(e, "fused x+y sweep launch");
+        }
+        for (int a = fused ? 2 : 0; a < p->ndim; ++a) {
             int flags = 0;
             if (a == 0) flags |= F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
             if (imag && a == p->ndim - 1) flags |= F_NORM_OUT;

@@ -26,6 +26,7 @@ enum KernelKind {
     K_BATCH = 10,
     K_COPY = 11,
     K_NORM_FINAL = 12,
+    K_SWEEP_XY = 13,
 };
 
 // Flags of the line-sweep kernel.
@@ -131,6 +132,8 @@ struct gp_plan {
     double *d_obs = nullptr;        // observable partials + final sums
     int64_t n_obs_blocks = 0;
     int64_t device_bytes = 0;
+    int xy_segs = 0;                // 3D: row segments per plane of the fused x+y kernel (0: not fusable)
+    bool xy_enabled = true;         // use the fused kernel when xy_segs > 0 (default: complex128)
     gp::Timing timing;
 };
 
@@ -157,6 +160,10 @@ hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
 inline double *norm_partials(gp_plan *p, int64_t step) { return p->d_norm + (step & 1) * p->n_norm; }
 inline double *norm_total(gp_plan *p, int64_t step) { return p->d_norm + 2 * p->n_norm + (step & 1); }
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
+// Fused x and y sweeps of a 3D step (src -> dst, x flags as for the x sweep).
+hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
+size_t xy_lds_bytes(const gp_plan *p);
+int xy_choose_segments(const gp_plan *p, int64_t max_lds);  // 0: the shape is not fusable
 constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
 constexpr int kXLinesPerGroup = 16; // lines per workgroup of the x scan kernel (4 per wavefront)
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel

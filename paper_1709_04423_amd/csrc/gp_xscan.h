@@ -96,6 +96,74 @@ __device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict
     }
 }
 
+// Solves one line held as Q consecutive points per lane (u, in the potential
+// substep's output) and leaves the CN sweep's result in u, same layout.  Uses
+// only registers and cross-lane shuffles.
+// xmul: multipliers of this lane's composed maps before each scan step (host
+// table: rows s = 0..5 forward, 6..11 backward, one value per lane); S: scan steps.
+template <typename R, int MODE, int Q>
+__device__ __forceinline__ void x_line_solve(const SweepParams &P, const typename CT<R>::V *__restrict__ tab,
+                                             const typename CT<R>::V *__restrict__ xmul, int S, int lane,
+                                             cp<R> (&u)[Q])
+{
+    using V = typename CT<R>::V;
+    const int64_t q0 = (int64_t)lane * Q;
+    const cp<R> zero = {R(0), R(0)};
+    cp<R> left = shfl_up_c(u[Q - 1], 1);
+    cp<R> right = shfl_down_c(u[0], 1);
+    if (lane == 0) left = zero;
+    if (lane == kLanes - 1) right = zero;
+
+    // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
+    // table rows: kernel-argument constants except on the first few lanes
+    cp<R> f[Q], ac[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const cp<R> um1 = i == 0 ? left : u[i - 1];
+        const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
+        V c, b, blo;
+        row_of<R>(P, tab, q0 + i, c, b, blo);
+        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
+        f[i] = kmul<MODE>(from_v<R>(c), rhs);
+        ac[i] = {-c.x, MODE == GP_IMAG ? R(0) : -c.y};
+    }
+    cp<R> F = f[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac[i], F, f[i]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        if (s < S) {  // uniform
+            const cp<R> Fp = shfl_up_c(F, 1 << s);
+            if (lane >= (1 << s)) F = kfma<MODE>(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
+        }
+    }
+    cp<R> y = shfl_up_c(F, 1);
+    if (lane == 0) y = zero;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        y = kfma<MODE>(ac[i], y, f[i]);
+        f[i] = y;
+    }
+    // backward: u'_p = a_p u'_{p+1} + y_p
+    cp<R> G = f[Q - 1];
+#pragma unroll
+    for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac[i], G, f[i]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        if (s < S) {  // uniform
+            const cp<R> Gp = shfl_down_c(G, 1 << s);
+            if (lane + (1 << s) < kLanes) G = kfma<MODE>(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
+        }
+    }
+    cp<R> v = shfl_down_c(G, 1);
+    if (lane == kLanes - 1) v = zero;
+#pragma unroll
+    for (int i = Q - 1; i >= 0; --i) {
+        v = kfma<MODE>(ac[i], v, f[i]);
+        u[i] = v;
+    }
+}
+
 // Each wavefront solves kXLines lines in turn.  Everything that depends only
 // on the position along the line is computed once: the table rows of the
 // lane's points are loaded before the line loop, and the multiplier halves of
@@ -120,9 +188,6 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     auto pad = [](int q) { return q + q / Q; };  // slot of point q in xl
     const int S = P.scan_steps;
     const cp<R> zero = {R(0), R(0)};
-
-    // multipliers of this lane's composed maps before each scan step (host table:
-    // rows s = 0..5 forward, 6..11 backward, one value per lane)
     const V *__restrict__ xmul = (const V *)P.xmul;
     const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
     V nxt[Q];  // the next line's values, loaded while the current one is solved
@@ -158,59 +223,7 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
 #pragma unroll
             for (int i = 0; i < Q; ++i) u[i] = from_v<R>(xl[pad(lane * Q + i)]);
         }
-        cp<R> left = shfl_up_c(u[Q - 1], 1);
-        cp<R> right = shfl_down_c(u[0], 1);
-        if (lane == 0) left = zero;
-        if (lane == kLanes - 1) right = zero;
-
-        // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
-        // table rows: kernel-argument constants except on the first few lanes
-        cp<R> f[Q], ac[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const cp<R> um1 = i == 0 ? left : u[i - 1];
-            const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
-            V c, b, blo;
-            row_of<R>(P, tab, q0 + i, c, b, blo);
-            const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
-            f[i] = kmul<MODE>(from_v<R>(c), rhs);
-            ac[i] = {-c.x, MODE == GP_IMAG ? R(0) : -c.y};
-        }
-        cp<R> F = f[0];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac[i], F, f[i]);
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            if (s < S) {  // uniform
-                const cp<R> Fp = shfl_up_c(F, 1 << s);
-                if (lane >= (1 << s)) F = kfma<MODE>(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
-            }
-        }
-        cp<R> y = shfl_up_c(F, 1);
-        if (lane == 0) y = zero;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            y = kfma<MODE>(ac[i], y, f[i]);
-            f[i] = y;
-        }
-        // backward: u'_p = a_p u'_{p+1} + y_p
-        cp<R> G = f[Q - 1];
-#pragma unroll
-        for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac[i], G, f[i]);
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            if (s < S) {  // uniform
-                const cp<R> Gp = shfl_down_c(G, 1 << s);
-                if (lane + (1 << s) < kLanes) G = kfma<MODE>(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
-            }
-        }
-        cp<R> v = shfl_down_c(G, 1);
-        if (lane == kLanes - 1) v = zero;
-#pragma unroll
-        for (int i = Q - 1; i >= 0; --i) {
-            v = kfma<MODE>(ac[i], v, f[i]);
-            u[i] = v;
-        }
+        x_line_solve<R, MODE, Q>(P, tab, xmul, S, lane, u);
         if (Q > 1) {  // back to the coalesced layout
 #pragma unroll
             for (int i = 0; i < Q; ++i) xl[pad(lane * Q + i)] = to_v<V>(u[i]);
