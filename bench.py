@@ -10,6 +10,11 @@ then floor(K/2) real-time steps in complex128 (the reported value), and the
 same again with complex64 bulk arithmetic and FP64 reductions (reported beside
 it with its chemical-potential error against the complex128 run).
 
+The chosen forms are reported beside it: complex64 bulk (``fp32``), the batched
+form (``batch``: 64 uneven 2D problems, 1000 real-time steps in one autotuned
+call) and the adjoint form (``adjoint``: gradient of a final-state loss over
+2000 real-time steps of a 256^2 grid, both precisions).
+
 value = grid points x steps / time of the gp_step calls (inputs resident in HBM,
 HIP-event timing on the launch stream).  One JSON line is printed on stdout.
 """
@@ -40,6 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the complex64 run")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and adjoint forms")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -116,6 +122,72 @@ def copy_probe(torch, binding, nbytes=1 << 30, reps=10):
     gbps = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
     del src, dst
     return gbps
+
+
+def batch_form(torch, binding, inputs, steps=1000):
+    """Batched form: the 64 uneven 2D problems (sides from {128..512}, dx = 0.05,
+    dt = 1e-3, g ~ U[10, 500], nu ~ U[0.5, 2]), complex64 bulk, autotuned launch,
+    `steps` real-time steps in one gp_batch_step call."""
+    import tempfile
+    probs = inputs.batch_problems()
+    b = binding.Batch([p.n for p in probs], 0.05, 1e-3, binding.GP_REAL, [p.omega for p in probs],
+                      [p.g for p in probs], binding.GP_C64)
+    cache = os.path.join(tempfile.gettempdir(), "sscn_batch_tune.txt")
+    cfg = b.autotune(cache)
+    psis = [torch.from_numpy(inputs.gaussian(p.n, p.dx, p.omega).astype("complex64")).to("cuda") for p in probs]
+    b.step(psis, 10)
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    b.step(psis, steps)
+    e.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e)
+    pts = sum(p.points for p in probs)
+    v = pts * steps / (ms * 1e-3)
+    return {"value": v, "unit": "grid-point updates/s", "problems": len(probs), "points": pts, "steps": steps,
+            "ms_per_step": ms / steps, "dtype": "c64 bulk, f64 reductions", "config": cfg,
+            "hbm_frac": 32 * v / 1e9 / HBM_PEAK_GBPS,
+            "note": "2D: 32 B per point-step (one complex64 read and write per sweep, two sweeps)"}
+
+
+def adjoint_form(torch, binding, inputs):
+    """Adjoint form: 256^2, dx = 0.05, dt = 1e-3, g = 200, T = 2000 real-time steps with a
+    seeded trap schedule; forward (sqrt(T) checkpoints) and backward (recompute +
+    hand-written adjoint kernels) through torch.autograd, in both precisions."""
+    from paper_1709_04423_amd import adjoint
+    w = inputs.ADJOINT_2D
+    sched = inputs.gamma_schedule(w.steps)
+    psi0 = inputs.gaussian(w.n, w.dx, (1.0, 1.0))
+    tgt = inputs.gaussian(w.n, w.dx, (1.5, 1.0))
+    out = {}
+    for name, dt_ in (("c128", torch.complex128), ("c64", torch.complex64)):
+        # untimed warm-up: loads the kernels this form launches
+        pw = torch.from_numpy(psi0).to("cuda").to(dt_).requires_grad_(True)
+        sw = torch.tensor(sched[:20], dtype=torch.float64, device="cuda", requires_grad=True)
+        adjoint.overlap_loss(adjoint.evolve(pw, sw, w.g, w.n, w.dx, w.dt, (1.0, 1.0)),
+                             torch.from_numpy(tgt).to("cuda").to(dt_), w.dx).backward()
+        psi = torch.from_numpy(psi0).to("cuda").to(dt_).requires_grad_(True)
+        s = torch.tensor(sched, dtype=torch.float64, device="cuda", requires_grad=True)
+        g = torch.tensor(w.g, dtype=torch.float64, device="cuda", requires_grad=True)
+        tg = torch.from_numpy(tgt).to("cuda").to(dt_)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = adjoint.overlap_loss(adjoint.evolve(psi, s, g, w.n, w.dx, w.dt, (1.0, 1.0)), tg, w.dx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        # forward T steps, backward T recomputed steps + T adjoint steps
+        pts = w.points * w.steps
+        out[name] = {"forward_s": t1 - t0, "backward_s": t2 - t1, "gradient_s": t2 - t0,
+                     "point_updates_per_s": 3 * pts / (t2 - t0), "loss": float(loss.item()),
+                     "dg": float(g.grad.item())}
+    out["workload"] = "2d_256sq_T2000_real_adjoint"
+    out["note"] = ("wall time of loss.backward() after a checkpointed forward; point updates count the "
+                   "forward, the recomputed and the adjoint steps")
+    return out
 
 
 def cpu_baseline(w, psi0_np, budget_s):
@@ -223,6 +295,16 @@ def main():
                 "energy_rel_err_after_real_phase": abs(real32["energy"] - real64["energy"]) / abs(real64["energy"])}
         log(f"complex64: {ms32:.1f} ms -> {v32:.3e} point-updates/s, mu err {fp32['mu_rel_err_vs_c128']:.2e}")
 
+    batch = None
+    if not args.no_forms:
+        batch = batch_form(torch, binding, inputs)
+        log(f"batch form: {batch['value']:.3e} point-updates/s ({batch['ms_per_step']:.3f} ms/step, "
+            f"config {batch['config']})")
+    adj = None
+    if not args.no_forms:
+        adj = adjoint_form(torch, binding, inputs)
+        log(f"adjoint form: c128 gradient {adj['c128']['gradient_s']:.3f} s, c64 {adj['c64']['gradient_s']:.3f} s")
+
     gbps = copy_probe(torch, binding)
     log(f"copy probe: {gbps:.0f} GB/s")
     cpu = None
@@ -254,6 +336,8 @@ def main():
         "per_kernel": per_kernel,
         "copy_probe_GBps": round(gbps, 1),
         "fp32": fp32,
+        "batch": batch,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -153,6 +153,14 @@ const char *gp_last_error(void);
 
 /* ------------------------------------------------------ adjoint form */
 
+/* `nsteps` real-time steps of psi in place (as gp_step), storing the input of
+ * each: states (device, nsteps consecutive grids of psi's precision and
+ * layout, caller-owned) receives states[k] = psi before step (current step
+ * index) + k.  This is what gp_step_adjoint consumes; a recomputed segment of
+ * the checkpointed reverse sweep is one call.  Real-time plans only
+ * (GP_EUNSUPPORTED otherwise).  Asynchronous. */
+gp_status gp_step_record(gp_plan *plan, void *psi, int64_t nsteps, void *states, void *stream);
+
 /* Reverse of `nsteps` real-time steps n_first .. n_first+nsteps-1, in the
  * gradient convention G = dL/dRe + i dL/dIm (PyTorch's for a real loss).
  *   states : device, nsteps consecutive wavefunctions; states[k] is the INPUT

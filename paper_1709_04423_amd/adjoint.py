@@ -64,9 +64,7 @@ class _SSCNEvolve(torch.autograd.Function):
             m = min(S, T - k0)
             psi = checkpoints[seg].clone()
             plan.set_step(k0)
-            for i in range(m):  # recompute the segment, keeping every step's input
-                states[i].copy_(psi)
-                plan.step(psi, 1)
+            plan.step_record(psi, m, states)  # recompute the segment, keeping every step's input
             plan.adjoint(states, lam, k0, m, dsched[k0:k0 + m], dg)
         return (lam, dsched.to(ctx.sched_dtype), dg.reshape(()).to(ctx.g_dtype), None, None, None, None, None,
                 None)

@@ -74,6 +74,7 @@ def lib():
             "gp_plan_set_xy_fusion": [vp, i32],
             "gp_thomas_table": [i64, d, d, i32, i32, i32, c_dp, c_dp, ctypes.POINTER(ctypes.c_int), c_dp],
             "gp_step_adjoint": [vp, vp, vp, i64, i64, vp, vp, vp],
+            "gp_step_record": [vp, vp, i64, vp, vp],
             "gp_batch_create": [pp, i32, c_i64p, c_dp, c_dp, i32, c_dp, c_dp, i32],
             "gp_batch_destroy": [vp],
             "gp_batch_step": [vp, pp, i64, vp],
@@ -203,6 +204,16 @@ class Plan:
         check(lib().gp_observables(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.byref(o),
                                    _stream_handle(stream)), "gp_observables")
         return o.as_dict()
+
+    def step_record(self, psi, nsteps: int, states, stream=None):
+        """nsteps real-time steps of psi in place, states[k] = input of the k-th one."""
+        _check_psi(psi, self.shape, self.prec)
+        if not states.is_cuda or states.dtype != psi.dtype or not states.is_contiguous() or states.dim() != psi.dim() + 1 \
+                or tuple(states.shape[1:]) != tuple(psi.shape) or states.shape[0] < nsteps:
+            raise ValueError("states must be a contiguous (>= nsteps, *psi.shape) tensor of psi's dtype")
+        check(lib().gp_step_record(self._h, ctypes.c_void_p(psi.data_ptr()), int(nsteps),
+                                   ctypes.c_void_p(states.data_ptr()), _stream_handle(stream)), "gp_step_record")
+        return psi
 
     def set_step(self, step: int):
         check(lib().gp_plan_set_step(self._h, int(step)), "gp_plan_set_step")

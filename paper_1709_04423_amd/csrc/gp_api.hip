@@ -617,6 +617,23 @@ gp_status gp_observables(gp_plan *p, const void *psi, gp_obs *out, void *stream)
     return GP_OK;
 }
 
+gp_status gp_step_record(gp_plan *p, void *psi, int64_t nsteps, void *states, void *stream)
+{
+    if (!p || !psi || !states || nsteps < 0) return set_error("bad argument"), GP_EINVAL;
+    if (p->mode != GP_REAL) return set_error("recording needs a real-time plan"), GP_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t bytes = (size_t)p->npts * elem_bytes(p->prec);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        e = launch_copy((char *)states + (size_t)k * bytes, psi, (int64_t)bytes, s);
+        if (e != hipSuccess) return hip_fail(e, "state copy launch");
+        const gp_status st = gp_step(p, psi, 1, stream);
+        if (st != GP_OK) return st;
+    }
+    return GP_OK;
+}
+
 gp_status gp_step_adjoint(gp_plan *p, const void *states, void *lambda, int64_t n_first, int64_t nsteps,
                           double *dsched, double *dg, void *stream)
 {

@@ -178,3 +178,23 @@ def test_autograd_fp32_gradient_error(gp):
     err = np.max(np.abs(s.grad.cpu().numpy() - dsr)) / np.max(np.abs(dsr))
     say(f"fp32 schedule-gradient error {err:.2e}")
     assert err < 1e-3
+
+
+def test_step_record_stores_each_step_input(gp):
+    n, dx, dt, omega, g, m = (48, 40, 36), (0.2, 0.2, 0.25), 1e-3, (1.0, 1.5, 2.0), 60.0, 5
+    psi0 = to_dev(inputs.noisy_gaussian(n, dx, omega, 44))
+    plan = gp.Plan(n, dx, dt, gp.GP_REAL, omega, g)
+    psi = psi0.clone()
+    states = torch.empty((m,) + tuple(n[::-1]), dtype=psi.dtype, device="cuda")
+    plan.step_record(psi, m, states)
+    ref = gp.Plan(n, dx, dt, gp.GP_REAL, omega, g)
+    chk = psi0.clone()
+    for k in range(m):
+        assert torch.equal(states[k], chk), k
+        ref.step(chk, 1)
+    assert torch.equal(psi, chk)
+    assert plan.info()["step"] == m
+    imag = gp.Plan(n, dx, dt, gp.GP_IMAG, omega, g)
+    with pytest.raises(gp.GpError) as e:
+        imag.step_record(psi0.clone(), 2, states)
+    assert e.value.status == gp.GP_EUNSUPPORTED
