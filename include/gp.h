@@ -203,7 +203,8 @@ gp_status gp_batch_destroy(gp_batch *batch);
 gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream);
 
 /* Time candidate configurations -- persistent or phased launch, x lines per
- * work item (1, 2, 4), y segments per line (1, 2, 4, 8), persistent grid size
+ * work item (1, 2, 4), y segments per line (1..32, capped per problem by the
+ * segments its y window allows), persistent grid size
  * (256..2048 workgroups) -- for 10 steps each on scratch copies of the problems
  * and keep the fastest.  cache_path (may be NULL): text file of previous
  * results, one line "key persistent lines ysegs grid" per batch shape (key: the
@@ -216,7 +217,8 @@ gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *strea
  * stalled launch, and for exercising the GP_ETIMEOUT path. */
 gp_status gp_batch_set_wait_limit(gp_batch *batch, uint32_t polls);
 
-/* Read / set the configuration explicitly (persistent = 1 needs real time). */
+/* Read / set the configuration explicitly (persistent = 1 needs real time;
+ * lines 1..64, ysegs 1..64, grid 1..65536; GP_EINVAL outside). */
 gp_status gp_batch_get_config(const gp_batch *batch, int *persistent, int *lines, int *ysegs, int *grid);
 gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ysegs, int grid);
 

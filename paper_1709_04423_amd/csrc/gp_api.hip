@@ -117,7 +117,10 @@ static void table_rows(const std::vector<std::complex<long double>> &c, int64_t 
 // exact two-pass solver when K + 1 > kMaxWindowPoints or the ring (plus the
 // transposed tile) does not fit in LDS.  Lines are split into segments until
 // about two (complex128) or four (complex64) wavefronts per SIMD are in
-// flight, keeping every segment at least four windows long.
+// flight, keeping every segment at least four windows long; grids too small for
+// one wavefront per SIMD are split further, down to one window per segment.
+constexpr int64_t kMinSweepWaves = 1024;  // one wavefront per SIMD of a 256-CU device
+
 static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
 {
     const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
@@ -145,8 +148,13 @@ static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
         const int64_t waves = (A.nlines + kLanes - 1) / kLanes;
         // about 2 wavefronts per SIMD for complex128 rows, 4 for complex64 (same bytes in flight)
         const int64_t target = prec == GP_C128 ? 2048 : 4096;
-        if (!tile)
+        if (!tile) {
             while (A.segs < 8 && waves * A.segs < target && nblocks / (A.segs + 1) >= 4 * (D + 1)) ++A.segs;
+            // small grids leave the device mostly idle and each wavefront's
+            // sequential chain sets the time: keep splitting, down to segments
+            // of one window, until about one wavefront per SIMD is busy
+            while (A.segs < 64 && waves * A.segs < kMinSweepWaves && nblocks / (A.segs + 1) >= D + 1) ++A.segs;
+        }
     } else {
         A.K = -1;
         A.D = 0;

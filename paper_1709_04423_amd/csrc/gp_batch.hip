@@ -581,7 +581,7 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
     }
     std::vector<BatchConfig> cands;
     for (int lines : {1, 2, 4})
-        for (int ysegs : {1, 2, 4, 8}) {
+        for (int ysegs : {1, 2, 4, 8, 16, 32}) {
             BatchConfig c;
             c.spin_limit = b->cfg.spin_limit;
             c.persistent = 0;
@@ -657,7 +657,7 @@ gp_status gp_batch_get_config(const gp_batch *b, int *persistent, int *lines, in
 
 gp_status gp_batch_set_config(gp_batch *b, int persistent, int lines, int ysegs, int grid)
 {
-    if (!b || persistent < 0 || persistent > 1 || lines < 1 || lines > 64 || ysegs < 1 || ysegs > 8 || grid < 1 ||
+    if (!b || persistent < 0 || persistent > 1 || lines < 1 || lines > 64 || ysegs < 1 || ysegs > 64 || grid < 1 ||
         grid > 65536)
         return set_error("bad argument"), GP_EINVAL;
     if (persistent && b->mode != GP_REAL) return set_error("persistent batches run real time only"), GP_EUNSUPPORTED;

@@ -134,6 +134,23 @@ def test_real_time_fp32_table_is_unitary_in_the_interior():
     assert abs(np.linalg.norm(v) / np.linalg.norm(u) - 1) < 1e-13
 
 
+@pytest.mark.parametrize("mode", [binding.GP_IMAG, binding.GP_REAL])
+@pytest.mark.parametrize("prec", [binding.GP_C128, binding.GP_C64])
+def test_windowed_solve_with_one_window_per_segment(mode, prec):
+    # small grids are split down to segments of D + 1 blocks; each still matches
+    # the dense solve to the window bound
+    n, dx, dt = 256, 0.05, 1e-3
+    c, beta, K, rho = binding.thomas_table(n, dx, dt, mode, prec)
+    A, B = cn_dense(n, dx, dt, mode)
+    u = np.random.default_rng(11).standard_normal(n) + 1j * np.random.default_rng(12).standard_normal(n)
+    ref = np.linalg.solve(A, B @ u) if prec == binding.GP_C128 else solve_with_table(c, beta, u)
+    D = (K + 1 + BLOCK - 1) // BLOCK
+    segs = ((n + BLOCK - 1) // BLOCK) // (D + 1)
+    got = solve_windowed(c, beta, u, K, BLOCK, segs)
+    tol = 1e-14 if prec == binding.GP_C128 else 1e-12
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
 def test_window_depth_and_exact_fallback():
     # K = D*4 - 1 for the smallest D whose window meets the bound
     _, _, K, rho = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C128)
