@@ -177,6 +177,10 @@ static void x_scan_setup(AxisPlan &A, const std::vector<std::complex<long double
     while ((int64_t)Q * kLanes < A.n) Q <<= 1;
     if (Q > kXMaxQ) return;
     A.xq = Q;
+    // lines per wavefront: 4 on large grids (the next line's load overlaps the
+    // current solve), fewer while that would leave under 1024 workgroups
+    A.xlpw = 4;
+    while (A.xlpw > 1 && A.nlines < (int64_t)1024 * kXWavesPerGroup * A.xlpw) A.xlpw >>= 1;
     int S = 0;
     while (S < 6 && (int64_t)Q * (1 << S) <= A.kmin) ++S;
     A.scan_steps = S;

@@ -63,6 +63,7 @@ struct SweepParams {
     double b_inf[3];      // beta_q (re, im hi, im lo)
     const void *xmul;     // x scan multipliers: 12 rows x 64 lanes (forward steps 0..5, backward 0..5)
     int xq;               // x scan points per lane (0: not the scan kernel)
+    int xlpw;             // x scan lines per wavefront
     // potential substep on axis 0
     double dt, g;
     double hw2[3];        // 1/2 omega_a^2 of this step
@@ -89,6 +90,7 @@ struct AxisPlan {
     double bound = 0.0;
     int kmin = 0;         // smallest window meeting the precision's bound
     int xq = 0;           // x sweep: points per lane of the one-wavefront-per-line kernel (0: not used)
+    int xlpw = 1;         // x sweep: lines each wavefront solves in turn (1, 2 or 4)
     int scan_steps = 6;   // x sweep: Hillis-Steele steps (6 = full, exact)
     int64_t q_const = 0;  // first point from which every table row is identical
     double c_inf[2] = {0.0, 0.0}, b_inf[3] = {0.0, 0.0, 0.0};
@@ -165,7 +167,6 @@ hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t 
 size_t xy_lds_bytes(const gp_plan *p);
 int xy_choose_segments(const gp_plan *p, int64_t max_lds);  // 0: the shape is not fusable
 constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
-constexpr int kXLinesPerGroup = 16; // lines per workgroup of the x scan kernel (4 per wavefront)
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,

@@ -183,7 +183,7 @@ static hipError_t dispatch_flags(const AxisPlan &A, const SweepParams &P, int fl
 int64_t sweep_groups(const gp_plan *p, int axis)
 {
     const AxisPlan &A = p->ax[axis];
-    if (axis == 0 && A.xq > 0) return (A.nlines + kXLinesPerGroup - 1) / kXLinesPerGroup;
+    if (axis == 0 && A.xq > 0) return (A.nlines + kXWavesPerGroup * A.xlpw - 1) / (kXWavesPerGroup * A.xlpw);
     const int64_t g = (A.nlines + kLanes - 1) / kLanes;
     return A.K < 0 ? g : g * A.segs;
 }
@@ -239,6 +239,7 @@ SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void 
     P.b_inf[2] = sg * A.b_inf[2];
     P.xmul = adjoint ? A.d_xmul_adj : A.d_xmul;
     P.xq = A.xq;
+    P.xlpw = A.xlpw;
     return P;
 }
 

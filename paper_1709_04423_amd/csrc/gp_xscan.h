@@ -164,13 +164,12 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const typenam
     }
 }
 
-// Each wavefront solves kXLines lines in turn.  Everything that depends only
+// Each wavefront solves a run of lines in turn.  Everything that depends only
 // on the position along the line is computed once: the table rows of the
 // lane's points are loaded before the line loop, and the multiplier halves of
 // the lane's composed maps at every scan step come precomputed from the host
 // (their products involve only the table), so per line only the data halves
 // (the F and G of the affine maps) are composed and scanned.
-constexpr int kXLines = kXLinesPerGroup / kXWavesPerGroup;
 
 // One wavefront solves lines first .. first+count-1 (those below P.nlines),
 // adding its epilogue sums to nacc / acc_w / acc_g.

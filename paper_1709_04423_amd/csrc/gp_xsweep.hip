@@ -15,8 +15,8 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
     const int wave = threadIdx.x / kLanes;
     __shared__ typename CT<R>::V xl[kXWaves][kLanes * (Q + 1)];
     double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
-    x_scan_wave<R, MODE, FLAGS, Q>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * kXLines,
-                                   kXLines, nacc, acc_w, acc_g, xl[wave]);
+    x_scan_wave<R, MODE, FLAGS, Q>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw,
+                                   P.xlpw, nacc, acc_w, acc_g, xl[wave]);
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
         __shared__ double red[kXWaves][3];
         nacc = wave_sum(nacc);
@@ -48,7 +48,7 @@ template <typename R, int MODE, int FLAGS, int Q>
 static void launch_q(const SweepParams &P, const void *tab, hipStream_t s)
 {
     using V = typename CT<R>::V;
-    const int64_t per_group = (int64_t)kXWaves * kXLines;
+    const int64_t per_group = (int64_t)kXWaves * P.xlpw;
     const unsigned grid = (unsigned)((P.nlines + per_group - 1) / per_group);
     hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
                        (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
