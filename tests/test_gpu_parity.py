@@ -2,7 +2,7 @@
 element by element on the same seeded inputs.
 
 FP64 (complex128) bar: every element within 1e-12 of the oracle, relative to
-the largest |psi| (spec FP64 bar: 1e-12 relative), and observables within
+the largest |psi| (the FP64 parity bar: 1e-12 relative), and observables within
 1e-12 relative.  FP32-bulk (complex64) bar: 1e-5 relative on norm, mu and energy
 and on the elements (relative to max |psi|).
 """
