@@ -96,18 +96,41 @@ __device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict
     }
 }
 
+// Per-lane constants of the x solve: the table rows of the lane's Q points and
+// the multipliers of its composed maps before each of the first SMAX scan
+// steps (host table xmul: rows s = 0..5 forward, 6..11 backward, one value per
+// lane).  Loaded once, ahead of the line loop: loaded at their point of use,
+// each multiplier would be one more memory round trip per line, in sequence.
+template <typename R, int Q, int SMAX> struct XConsts {
+    using V = typename CT<R>::V;
+    V c[Q], b[Q], blo[Q];
+    V mf[SMAX], mb[SMAX];
+};
+
+template <typename R, int Q, int SMAX>
+__device__ __forceinline__ void x_consts_load(const SweepParams &P, const typename CT<R>::V *__restrict__ tab,
+                                              const typename CT<R>::V *__restrict__ xmul, int lane,
+                                              XConsts<R, Q, SMAX> &K)
+{
+    const int64_t q0 = (int64_t)lane * Q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) row_of<R>(P, tab, q0 + i, K.c[i], K.b[i], K.blo[i]);
+    const int last = P.scan_steps > 0 ? P.scan_steps - 1 : 0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {  // unconditional loads (steps past S are not used)
+        const int r = s < last ? s : last;
+        K.mf[s] = xmul[r * kLanes + lane];
+        K.mb[s] = xmul[(6 + r) * kLanes + lane];
+    }
+}
+
 // Solves one line held as Q consecutive points per lane (u, in the potential
 // substep's output) and leaves the CN sweep's result in u, same layout.  Uses
-// only registers and cross-lane shuffles.
-// xmul: multipliers of this lane's composed maps before each scan step (host
-// table: rows s = 0..5 forward, 6..11 backward, one value per lane); S: scan steps.
-template <typename R, int MODE, int Q>
-__device__ __forceinline__ void x_line_solve(const SweepParams &P, const typename CT<R>::V *__restrict__ tab,
-                                             const typename CT<R>::V *__restrict__ xmul, int S, int lane,
+// only registers and cross-lane shuffles; S <= SMAX scan steps.
+template <typename R, int MODE, int Q, int SMAX>
+__device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts<R, Q, SMAX> &K, int S, int lane,
                                              cp<R> (&u)[Q])
 {
-    using V = typename CT<R>::V;
-    const int64_t q0 = (int64_t)lane * Q;
     const cp<R> zero = {R(0), R(0)};
     cp<R> left = shfl_up_c(u[Q - 1], 1);
     cp<R> right = shfl_down_c(u[0], 1);
@@ -115,26 +138,23 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const typenam
     if (lane == kLanes - 1) right = zero;
 
     // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
-    // table rows: kernel-argument constants except on the first few lanes
     cp<R> f[Q], ac[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const cp<R> um1 = i == 0 ? left : u[i - 1];
         const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
-        V c, b, blo;
-        row_of<R>(P, tab, q0 + i, c, b, blo);
-        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, b, blo);
-        f[i] = kmul<MODE>(from_v<R>(c), rhs);
-        ac[i] = {-c.x, MODE == GP_IMAG ? R(0) : -c.y};
+        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, K.b[i], K.blo[i]);
+        f[i] = kmul<MODE>(from_v<R>(K.c[i]), rhs);
+        ac[i] = {-K.c[i].x, MODE == GP_IMAG ? R(0) : -K.c[i].y};
     }
     cp<R> F = f[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac[i], F, f[i]);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
         if (s < S) {  // uniform
             const cp<R> Fp = shfl_up_c(F, 1 << s);
-            if (lane >= (1 << s)) F = kfma<MODE>(from_v<R>(xmul[s * kLanes + lane]), Fp, F);
+            if (lane >= (1 << s)) F = kfma<MODE>(from_v<R>(K.mf[s]), Fp, F);
         }
     }
     cp<R> y = shfl_up_c(F, 1);
@@ -149,10 +169,10 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const typenam
 #pragma unroll
     for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac[i], G, f[i]);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
         if (s < S) {  // uniform
             const cp<R> Gp = shfl_down_c(G, 1 << s);
-            if (lane + (1 << s) < kLanes) G = kfma<MODE>(from_v<R>(xmul[(6 + s) * kLanes + lane]), Gp, G);
+            if (lane + (1 << s) < kLanes) G = kfma<MODE>(from_v<R>(K.mb[s]), Gp, G);
         }
     }
     cp<R> v = shfl_down_c(G, 1);
@@ -174,7 +194,7 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const typenam
 // One wavefront solves lines first .. first+count-1 (those below P.nlines),
 // adding its epilogue sums to nacc / acc_w / acc_g.
 // xl: this wavefront's LDS buffer of x_lds_bytes<R>(Q) bytes.
-template <typename R, int MODE, int FLAGS, int Q>
+template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
 __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
                                             typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
                                             const typename CT<R>::V *__restrict__ state, int64_t first, int count,
@@ -187,7 +207,8 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     auto pad = [](int q) { return q + q / Q; };  // slot of point q in xl
     const int S = P.scan_steps;
     const cp<R> zero = {R(0), R(0)};
-    const V *__restrict__ xmul = (const V *)P.xmul;
+    XConsts<R, Q, SMAX> K;  // scan steps S <= SMAX
+    x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
     const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
     V nxt[Q];  // the next line's values, loaded while the current one is solved
 #pragma unroll
@@ -222,7 +243,7 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
 #pragma unroll
             for (int i = 0; i < Q; ++i) u[i] = from_v<R>(xl[pad(lane * Q + i)]);
         }
-        x_line_solve<R, MODE, Q>(P, tab, xmul, S, lane, u);
+        x_line_solve<R, MODE, Q, SMAX>(P, K, S, lane, u);
         if (Q > 1) {  // back to the coalesced layout
 #pragma unroll
             for (int i = 0; i < Q; ++i) xl[pad(lane * Q + i)] = to_v<V>(u[i]);

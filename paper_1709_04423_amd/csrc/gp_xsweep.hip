@@ -5,7 +5,7 @@
 
 namespace gp {
 
-template <typename R, int MODE, int FLAGS, int Q>
+template <typename R, int MODE, int FLAGS, int Q, int SMAX>
 __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P, const typename CT<R>::V *src,
                                                                    typename CT<R>::V *dst,
                                                                    const typename CT<R>::V *__restrict__ tab,
@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
     const int wave = threadIdx.x / kLanes;
     __shared__ typename CT<R>::V xl[kXWaves][kLanes * (Q + 1)];
     double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
-    x_scan_wave<R, MODE, FLAGS, Q>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw,
+    x_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw,
                                    P.xlpw, nacc, acc_w, acc_g, xl[wave]);
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
         __shared__ double red[kXWaves][3];
@@ -44,14 +44,20 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
     }
 }
 
+// Scan steps: most plans need at most 3 (a carry reaches Q 8 points); the
+// variant for up to 6 reserves registers for the longer scans.
 template <typename R, int MODE, int FLAGS, int Q>
 static void launch_q(const SweepParams &P, const void *tab, hipStream_t s)
 {
     using V = typename CT<R>::V;
     const int64_t per_group = (int64_t)kXWaves * P.xlpw;
     const unsigned grid = (unsigned)((P.nlines + per_group - 1) / per_group);
-    hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
-                       (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
+    if (P.scan_steps <= 3)
+        hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q, 3>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
+                           (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
+    else
+        hipLaunchKernelGGL((k_sweep_x_scan<R, MODE, FLAGS, Q, 6>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
+                           (const V *)P.psi, (V *)P.out, (const V *)tab, (const V *)P.state);
 }
 
 template <typename R, int MODE, int FLAGS>

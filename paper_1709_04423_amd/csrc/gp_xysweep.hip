@@ -26,6 +26,7 @@ namespace {
 
 constexpr int kXYWaves = 4;  // wavefronts per workgroup = rows per block of the y window
 constexpr int kXYAhead = 1;  // blocks whose rows are loaded ahead
+constexpr int kXYMaxScan = 3;  // x scan steps the fused kernel supports
 
 // Tile slot of point q of a row: the low three bits (one 128-byte group of
 // 16-byte values) are permuted by the next three, so the coalesced row
@@ -58,7 +59,10 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
     __shared__ V tile[B][kLanes * Q];
     extern __shared__ char ring_raw[];
     const int lane = threadIdx.x & (kLanes - 1);
-    const int w = threadIdx.x / kLanes;
+    // wave-uniform by construction; stated so, the y solver's table rows (whose
+    // addresses depend only on the block) are read as scalar loads, outside the
+    // vector memory counter that the prefetched rows occupy
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int64_t nx = PX.n, ny = PY.n;
     const int64_t k = blockIdx.y;  // plane
     const int cw = (int)(nx / kLanes);  // wavefronts with columns in the y part
@@ -71,8 +75,9 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
     const int j0 = Y.o_lo - DW > 0 ? Y.o_lo - DW : 0;
     const int j1 = Y.o_hi + DW;  // exclusive; uniform over the workgroup
 
-    const V *__restrict__ xmul = (const V *)PX.xmul;
-    const int S = PX.scan_steps;
+    const int S = PX.scan_steps;  // at most kXYMaxScan (checked on the host)
+    XConsts<R, Q, kXYMaxScan> KX;
+    x_consts_load<R, Q, kXYMaxScan>(PX, tabx, (const V *)PX.xmul, lane, KX);
     const double renorm = (XFLAGS & F_RENORM) ? 1.0 / sqrt(PX.dV * PX.norm_total[0]) : 1.0;
     // this wavefront's rows of the next kXYAhead blocks stay in flight while a
     // block is solved (one slot per block; the loop is unrolled over the slots so
@@ -91,7 +96,6 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
             cp<R> u[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) u[i] = from_v<R>(ahead[t][i]);
-            xy_load_row<R, Q>(src, j + kXYAhead, j1, w, k, nx, ny, lane, ahead[t]);
             if (y < ny) {  // uniform over the wavefront
                 LineCtx<R> L = line_ctx_of<R>(PX, y + ny * k);
                 if (XFLAGS & F_RENORM) L.scale = renorm;
@@ -107,13 +111,17 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
 #pragma unroll
                     for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot(lane * Q + i)]);
                 }
-                x_line_solve<R, MODE, Q>(PX, tabx, xmul, S, lane, u);
+                x_line_solve<R, MODE, Q, kXYMaxScan>(PX, KX, S, lane, u);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(u[i]);
             } else {  // rows past the plane are the y solver's zero rows
 #pragma unroll
                 for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(zero);
             }
+            // the next rows are requested only now: the vector memory counter is
+            // in order, so waiting for the x solve's table loads would otherwise
+            // wait for them too
+            xy_load_row<R, Q>(src, j + kXYAhead, j1, w, k, nx, ny, lane, ahead[t]);
             __syncthreads();
             if (w < cw) {
                 V buf[B];
@@ -182,6 +190,7 @@ int xy_choose_segments(const gp_plan *p, int64_t max_lds)
     if (p->ndim != 3) return 0;
     const AxisPlan &X = p->ax[0], &Y = p->ax[1];
     if (X.xq != 2 && X.xq != 4) return 0;
+    if (X.scan_steps > kXYMaxScan) return 0;
     if (p->n[0] % kLanes != 0 || p->n[0] > (int64_t)kLanes * X.xq) return 0;
     if (Y.K < 0 || Y.B != 4 || Y.D < 2 || Y.D > 4) return 0;
     if ((int64_t)xy_lds_bytes(p) > max_lds) return 0;
