@@ -480,8 +480,6 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
         max_lds = 0;
     p->xy_segs = xy_choose_segments(p, max_lds);
-    // complex64 runs its separate sweeps at higher occupancy, as fast as fused
-    p->xy_enabled = prec == GP_C128;
     *out = p;
     return GP_OK;
 }

@@ -135,7 +135,7 @@ struct gp_plan {
     int64_t n_obs_blocks = 0;
     int64_t device_bytes = 0;
     int xy_segs = 0;                // 3D: row segments per plane of the fused x+y kernel (0: not fusable)
-    bool xy_enabled = true;         // use the fused kernel when xy_segs > 0 (default: complex128)
+    bool xy_enabled = true;         // use the fused kernel when xy_segs > 0
     gp::Timing timing;
 };
 

@@ -80,8 +80,6 @@ def test_fused_step_fp32(gp, mode):
     n, dx, dt, omega, g, steps, _ = CASES[1]
     psi0 = initial(n, dx, omega, 8)
     plan = gp.Plan(n, dx, dt, mode, omega, g, gp.GP_C64)
-    assert plan.info()["xy_fused"] == 0  # complex64 defaults to separate sweeps
-    plan.set_xy_fusion(True)
     assert plan.info()["xy_fused"] >= 1
     psi = to_dev(psi0.astype(np.complex64))
     plan.step(psi, steps)
