@@ -75,38 +75,57 @@ template <typename R, int MODE, int FLAGS, int ACC, int DW, int BB> struct Windo
         }
     }
 
-    // Issue the loads of block j.
+    // Issue the loads of block j.  Every lane loads unconditionally from an
+    // in-bounds address (point index clamped to the line, inactive lanes on
+    // line 0); what lies outside the grid is zeroed only when the block is
+    // used (process).  Loads under branches, or a select right after them,
+    // would make the wavefront wait for them at once, the prefetched block
+    // included.
     __device__ __forceinline__ void load(V (&buf)[B], int j) const
     {
         const int64_t q0 = (int64_t)j * B;
         if (ACC == kStrided) {
 #pragma unroll
-            for (int k = 0; k < B; ++k) buf[k] = (L.active && q0 + k < n) ? src[base + (q0 + k) * stride] : zero();
+            for (int k = 0; k < B; ++k) {
+                const int64_t q = q0 + k;
+                buf[k] = src[base + (q < n ? q : n - 1) * stride];
+            }
         } else {
             const int pt = lane & (B - 1);
             const int64_t q = q0 + pt;
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const int64_t line = l0 + i * (kLanes / B) + lane / B;
-                buf[i] = (line < P.nlines && q < n) ? src[line * n + q] : zero();
+                buf[i] = src[(line < P.nlines ? line : P.nlines - 1) * n + (q < n ? q : n - 1)];
             }
         }
     }
 
-    // Solve block j (values in buf) and write output block j - DW if this segment owns it.
-    __device__ __forceinline__ void process(V (&buf)[B], int j)
+    // Whether the value load() put in slot k of block j lies on the grid.
+    __device__ __forceinline__ bool loaded_ok(int j, int k) const
+    {
+        if (ACC == kStrided) return L.active && (int64_t)j * B + k < n;
+        const int64_t line = l0 + k * (kLanes / B) + lane / B;
+        return line < P.nlines && (int64_t)j * B + (lane & (B - 1)) < n;
+    }
+
+    // Solve block j (values in buf, as load() left them; MASKED = false when the
+    // caller supplies values already zero off the grid) and write output block
+    // j - DW if this segment owns it.
+    template <bool MASKED = true> __device__ __forceinline__ void process(V (&buf)[B], int j)
     {
         V own[B];
         if (ACC == kTransposed) {
 #pragma unroll
-            for (int i = 0; i < B; ++i) tile[(i * (kLanes / B) + lane / B) * kPitch + (lane & (B - 1))] = buf[i];
+            for (int i = 0; i < B; ++i)
+                tile[(i * (kLanes / B) + lane / B) * kPitch + (lane & (B - 1))] = loaded_ok(j, i) ? buf[i] : zero();
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < B; ++k) own[k] = tile[lane * kPitch + k];
             __syncthreads();
         } else {
 #pragma unroll
-            for (int k = 0; k < B; ++k) own[k] = buf[k];
+            for (int k = 0; k < B; ++k) own[k] = (!MASKED || loaded_ok(j, k)) ? buf[k] : zero();
         }
         // forward elimination of points p = jB-1 .. jB+B-2 (u_{p+1} = own[k])
 #pragma unroll
@@ -204,11 +223,14 @@ __device__ __forceinline__ void window_run(const SweepParams &P, const typename 
     S.start(j0);
     V a[BB], b[BB];
     S.load(a, j0);
+    // the next block's loads are issued unconditionally (past the segment's end
+    // they repeat its last block, a cache hit): loads under a branch would make
+    // the wavefront wait for all of them before solving the current block
     for (int j = j0; j < j1; j += 2) {
-        if (j + 1 < j1) S.load(b, j + 1);
+        S.load(b, j + 1 < j1 ? j + 1 : j1 - 1);
         S.process(a, j);
         if (j + 1 >= j1) break;
-        if (j + 2 < j1) S.load(a, j + 2);
+        S.load(a, j + 2 < j1 ? j + 2 : j1 - 1);
         S.process(b, j + 1);
     }
     S.finish();

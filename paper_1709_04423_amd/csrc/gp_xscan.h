@@ -96,6 +96,23 @@ __device__ __forceinline__ void row_of(const SweepParams &P, const V *__restrict
     }
 }
 
+// Line `line` (clamped to the last line), coalesced: lane L gets points
+// L + 64 i (clamped to the last point).  Loads are unconditional from in-bounds
+// addresses and the caller zeroes points past n when it uses them: a load under
+// a branch, or a select right after it, would make the wavefront wait for it
+// at once, the prefetched line included.
+template <typename R, int Q>
+__device__ __forceinline__ void x_load_line(const typename CT<R>::V *src, int64_t line, int64_t nlines, int64_t n,
+                                            int lane, typename CT<R>::V (&dst)[Q])
+{
+    const int64_t lc = line < nlines ? line : nlines - 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t q = lane + kLanes * i;
+        dst[i] = src[lc * n + (q < n ? q : n - 1)];
+    }
+}
+
 // Per-lane constants of the x solve: the table rows of the lane's Q points and
 // the multipliers of its composed maps before each of the first SMAX scan
 // steps (host table xmul: rows s = 0..5 forward, 6..11 backward, one value per
@@ -211,9 +228,7 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
     const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
     V nxt[Q];  // the next line's values, loaded while the current one is solved
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-        nxt[i] = (first < P.nlines && lane + kLanes * i < n) ? src[first * n + lane + kLanes * i] : to_v<V>(zero);
+    x_load_line<R, Q>(src, first, P.nlines, n, lane, nxt);
 #pragma unroll 1
     for (int li = 0; li < count; ++li) {
         const int64_t line = first + li;
@@ -224,12 +239,10 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
 
         cp<R> u[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) u[i] = from_v<R>(nxt[i]);
+        for (int i = 0; i < Q; ++i) u[i] = lane + kLanes * i < n ? from_v<R>(nxt[i]) : zero;
         if (li + 1 < count) {
             const int64_t nl = line + 1;
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-                nxt[i] = (nl < P.nlines && lane + kLanes * i < n) ? src[nl * n + lane + kLanes * i] : to_v<V>(zero);
+            x_load_line<R, Q>(src, nl, P.nlines, n, lane, nxt);
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
                 V buf[B];
 #pragma unroll
                 for (int r = 0; r < B; ++r) buf[r] = tile[r][xy_slot(w * kLanes + lane)];
-                Y.process(buf, j);
+                Y.template process<false>(buf, j);  // tile rows are zero off the grid
             }
             __syncthreads();
         }
