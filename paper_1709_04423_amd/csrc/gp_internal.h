@@ -156,6 +156,11 @@ hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int fl
                         int64_t step_index, const void *state, hipStream_t s);
 SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void *dst, bool adjoint,
                               int64_t step_index, const void *state);
+// Windowed / two-pass sweep of one axis in one precision (gp_sweep_c128.hip, gp_sweep_c64.hip).
+hipError_t dispatch_sweep_c128(const AxisPlan &A, const SweepParams &P, gp_mode mode, int flags, bool exact,
+                               bool tr, const void *tab, hipStream_t s);
+hipError_t dispatch_sweep_c64(const AxisPlan &A, const SweepParams &P, gp_mode mode, int flags, bool exact,
+                              bool tr, const void *tab, hipStream_t s);
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s);
 hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
 // norm totals: one value per step parity, after the 2 x n_norm partials
