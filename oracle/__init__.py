@@ -56,6 +56,8 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         c_int, c_i64, c_d = ctypes.c_int, ctypes.c_int64, ctypes.c_double
         lib.oracle_num_threads.restype = c_int
+        lib.oracle_set_threads.argtypes = [c_int]
+        lib.oracle_set_threads.restype = None
         lib.oracle_thomas.argtypes = [c_i64, c_d, c_d, c_d, c_d, dp, dp]
         lib.oracle_cn_axis.argtypes = [c_int, i64p, dp, c_d, c_int, c_int, c_int, dp]
         lib.oracle_nonlinear.argtypes = [c_int, i64p, dp, c_d, c_int, dp, dp, c_i64, c_int,
@@ -107,6 +109,11 @@ def _c128(psi):
 
 def num_threads() -> int:
     return _load().oracle_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP line loops (results are independent of it)."""
+    _load().oracle_set_threads(int(n))
 
 
 def thomas(b: complex, e: complex, rhs: np.ndarray) -> np.ndarray:

@@ -385,46 +385,84 @@ def test_kohn_mode_of_displaced_ground_state():
 
 # ------------------------------------------------------------ adjoint
 
-def test_adjoint_step_matches_finite_differences():
-    n, dx, om, g, dt, T = (16, 12), (0.3, 0.35), (1.0, 1.0), 30.0, 5e-3, 20
-    psi0 = inputs.gaussian(n, dx, (1.0, 1.0)).astype(complex)
-    tgt = inputs.gaussian(n, dx, (1.4, 1.0))
-    sched = inputs.gamma_schedule(T)
+def _richardson(f, h):
+    d1 = (f(h) - f(-h)) / (2 * h)
+    d2 = (f(h / 2) - f(-h / 2)) / h
+    return (4 * d2 - d1) / 3
 
-    def loss(sc, gg):
-        psi = oracle.step(psi0, dx, dt, oracle.REAL, om, gg, T, sc, 0, 0)
+
+# The reverse sweep is pinned against central differences of the oracle's own
+# forward map on every branch it has: the schedule on x, y and z (the weight
+# x_s^2 of the schedule gradient comes from a different coordinate on each),
+# 2D and 3D grids (one, two or three adjoint CN sweeps), g, and the initial state.
+ADJOINT_CASES = [
+    # (grid x first, dx, trap, g, dt, T, schedule axis)
+    ((16, 12), (0.3, 0.35), (1.0, 1.0), 30.0, 5e-3, 20, 0),
+    ((12, 16), (0.35, 0.3), (1.0, 1.2), 25.0, 5e-3, 16, 1),
+    ((8, 10, 12), (0.45, 0.4, 0.35), (1.0, 1.3, 0.9), 15.0, 5e-3, 10, 2),
+    ((10, 8, 9), (0.4, 0.45, 0.42), (1.1, 0.9, 1.0), 12.0, 5e-3, 8, 1),
+]
+
+
+@pytest.mark.parametrize("case", ADJOINT_CASES, ids=lambda c: f"{len(c[0])}d-axis{c[6]}")
+def test_adjoint_matches_finite_differences(case):
+    n, dx, om, g, dt, T, ax = case
+    psi0 = inputs.gaussian(n, dx, om).astype(complex) + 0.02 * inputs.random_field(tuple(n[::-1]), 16)
+    tgt_om = list(om)
+    tgt_om[ax] = 1.4 * om[ax]
+    tgt = inputs.gaussian(n, dx, tgt_om)
+    sched = om[ax] * inputs.gamma_schedule(T)
+
+    def loss(sc, gg, p0=psi0):
+        psi = oracle.step(p0, dx, dt, oracle.REAL, om, gg, T, sc, ax, 0)
         return oracle.overlap_loss(psi, tgt, dx)[0]
 
-    L, dsched, dg, lam0 = oracle.gradient(psi0, tgt, dx, dt, om, g, sched)
+    L, dsched, dg, lam0 = oracle.gradient(psi0, tgt, dx, dt, om, g, sched, ax)
     assert abs(L - loss(sched, g)) < 1e-15
 
-    def richardson(f, h):
-        d1 = (f(h) - f(-h)) / (2 * h)
-        d2 = (f(h / 2) - f(-h / 2)) / h
-        return (4 * d2 - d1) / 3
-
-    rng = np.random.default_rng(13)
+    rng = np.random.default_rng(13 + ax)
     v = rng.standard_normal(T)
     v /= np.linalg.norm(v)
-    fd = richardson(lambda h: loss(sched + h * v, g), 1e-3)
+    fd = _richardson(lambda h: loss(sched + h * v, g), 1e-3)
     assert abs(fd - dsched @ v) <= 1e-8 * max(abs(fd), 1e-12) + 1e-12
-    for k in (0, 7, T - 1):
+    # single entries: rounding of the loss (~1e-16) divided by h = 1e-3 puts a
+    # noise floor of a few 1e-13 under each Richardson difference
+    for k in (0, T // 2, T - 1):
         e = np.zeros(T)
         e[k] = 1
-        fd = richardson(lambda h: loss(sched + h * e, g), 1e-3)
-        assert abs(fd - dsched[k]) <= 1e-8 * abs(dsched).max()
-    fd = richardson(lambda h: loss(sched, g + h), 1e-2)
+        fd = _richardson(lambda h: loss(sched + h * e, g), 1e-3)
+        assert abs(fd - dsched[k]) <= 1e-8 * abs(dsched).max() + 2e-12, k
+    fd = _richardson(lambda h: loss(sched, g + h), 1e-2)
     assert abs(fd - dg) <= 1e-8 * abs(dg)
     # gradient w.r.t. the initial state, along a random complex direction
     d = inputs.random_field(psi0.shape, 14)
     d /= np.linalg.norm(d)
-
-    def loss_psi(h):
-        psi = oracle.step(psi0 + h * d, dx, dt, oracle.REAL, om, g, T, sched, 0, 0)
-        return oracle.overlap_loss(psi, tgt, dx)[0]
-
-    fd = richardson(loss_psi, 1e-3)
+    fd = _richardson(lambda h: loss(sched, g, psi0 + h * d), 1e-3)
     assert abs(fd - np.vdot(lam0, d).real) <= 1e-8 * abs(fd)
+
+
+def test_adjoint_schedule_weight_uses_the_schedule_axis():
+    # the same step reversed with the schedule on each axis of an anisotropic 3D
+    # grid: the schedule gradients differ by the weight x_s^2 alone, so with the
+    # gradient lambda and the state fixed they must reproduce sum w x_s^2 for the
+    # matching coordinate (a swapped axis index gives a different, nonzero value)
+    n, dx, om, g, dt = (6, 8, 10), (0.5, 0.4, 0.3), (1.0, 1.0, 1.0), 20.0, 1e-2
+    psi = inputs.gaussian(n, dx, om) + 0.1 * inputs.random_field((10, 8, 6), 17)
+    lam = inputs.random_field((10, 8, 6), 18)
+    x = [coords(n[a], dx[a]) for a in range(3)]
+    X2 = [x[0][None, None, :] ** 2 * np.ones((10, 8, 6)), x[1][None, :, None] ** 2 * np.ones((10, 8, 6)),
+          x[2][:, None, None] ** 2 * np.ones((10, 8, 6))]
+    got = [oracle.adjoint_step(psi, lam, dx, dt, om, g, np.array([1.0]), a, 0)[1] for a in range(3)]
+    # w from the definition: lambda_u = CN adjoints of lambda, u = psi e^{-i theta}
+    lu = lam
+    for a in (2, 1, 0):
+        lu = oracle.cn_axis(lu, dx, dt, oracle.REAL, a, adjoint=True)
+    V = 0.5 * (X2[0] + X2[1] + X2[2])
+    u = psi * np.exp(-1j * dt * (V + g * np.abs(psi) ** 2))
+    w = (np.conj(lu) * u).imag
+    for a in range(3):
+        assert abs(got[a] - dt * np.sum(w * X2[a])) <= 1e-12 * abs(got[a]), a
+    assert len({round(v, 12) for v in got}) == 3
 
 
 def test_threads_do_not_change_results():
