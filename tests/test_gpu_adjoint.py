@@ -114,56 +114,6 @@ def test_fp64_long_real_run_matches_oracle(gp):
         assert abs(o[k] - r[k]) <= 1e-12 * abs(r[k])
 
 
-def _adjoint_workload():
-    """256^2, dx = 0.05, dt = 1e-3, g = 200, T = 2000, gamma_n ~ U[0.8, 1.2]; start and
-    target near the imaginary-time ground states at gamma = 1 and 1.5 (oracle runs)."""
-    w = inputs.ADJOINT_2D
-    sched = inputs.gamma_schedule(w.steps)
-    psi0 = oracle.step(inputs.gaussian(w.n, w.dx, (1.0, 1.0)), w.dx, 1e-3, oracle.IMAG, (1.0, 1.0), w.g, 400)
-    tgt = oracle.step(inputs.gaussian(w.n, w.dx, (1.5, 1.0)), w.dx, 1e-3, oracle.IMAG, (1.5, 1.0), w.g, 400)
-    return w, sched, psi0, tgt
-
-
-def test_autograd_full_adjoint_workload_matches_oracle_and_fd(gp):
-    from paper_1709_04423_amd import adjoint
-    w, sched, psi0, tgt = _adjoint_workload()
-    say("autograd 256^2 T=2000")
-    psi = to_dev(psi0).requires_grad_(True)
-    s = torch.tensor(sched, dtype=torch.float64, device="cuda", requires_grad=True)
-    g = torch.tensor(w.g, dtype=torch.float64, device="cuda", requires_grad=True)
-    tg = to_dev(tgt)
-    loss = adjoint.overlap_loss(adjoint.evolve(psi, s, g, w.n, w.dx, w.dt, (1.0, 1.0)), tg, w.dx)
-    loss.backward()
-    ds, dg, dpsi = s.grad.cpu().numpy(), float(g.grad.item()), psi.grad.cpu().numpy()
-    say("oracle gradient")
-    Lr, dsr, dgr, lamr = oracle.gradient(psi0, tgt, w.dx, w.dt, (1.0, 1.0), w.g, sched)
-    say(f"  loss {loss.item():.15f} oracle {Lr:.15f}")
-    assert abs(loss.item() - Lr) <= 1e-12 * abs(Lr)
-    assert np.max(np.abs(ds - dsr)) <= 1e-9 * np.max(np.abs(dsr))
-    assert abs(dg - dgr) <= 1e-9 * abs(dgr)
-    assert np.max(np.abs(dpsi - lamr)) <= 1e-9 * np.max(np.abs(lamr))
-
-    # central differences with Richardson extrapolation on the GPU forward path
-    def loss_at(sc, gg):
-        with torch.no_grad():
-            out = adjoint.evolve(to_dev(psi0), torch.tensor(sc, device="cuda"), gg, w.n, w.dx, w.dt, (1.0, 1.0))
-            return float(adjoint.overlap_loss(out, tg, w.dx).item())
-
-    def richardson(f, h):
-        d1 = (f(h) - f(-h)) / (2 * h)
-        d2 = (f(h / 2) - f(-h / 2)) / h
-        return (4 * d2 - d1) / 3
-
-    v = np.random.default_rng(41).standard_normal(len(sched))
-    v /= np.linalg.norm(v)
-    fd_s = richardson(lambda h: loss_at(sched + h * v, w.g), 1e-3)
-    fd_g = richardson(lambda h: loss_at(sched, w.g + h), 1e-2)
-    rel_s = abs(fd_s - ds @ v) / abs(fd_s)
-    rel_g = abs(fd_g - dg) / abs(fd_g)
-    say(f"  FD check: schedule {rel_s:.2e}, g {rel_g:.2e}")
-    assert rel_s <= 1e-6 and rel_g <= 1e-6
-
-
 def test_autograd_fp32_gradient_error(gp):
     from paper_1709_04423_amd import adjoint
     n, dx, dt, g, T = (96, 80), (0.15, 0.15), 1e-3, 200.0, 200
