@@ -61,8 +61,8 @@ typedef enum { GP_C128 = 0, GP_C64 = 1 } gp_prec;
 
 /* Harmonic trap V = 1/2 sum_a omega[a]^2 x_a^2.  Optionally a host array of
  * per-step frequencies replaces omega[sched_axis] in the potential substep of
- * step n for 0 <= n < sched_len (the plan copies it).  Observables always use
- * the static omega[]. */
+ * step n for 0 <= n < sched_len (the plan copies it); later steps use the
+ * static omega[].  Observables use the trap of the plan's last step. */
 typedef struct {
     double omega[3];
     const double *omega_sched;
@@ -100,9 +100,13 @@ typedef struct gp_batch gp_batch;
 
 /* Create a plan for an ndim-dimensional grid n[0..ndim) (x first) with
  * spacings dx[0..ndim), time step dt > 0, mode, trap (may be NULL: all
- * omega = 0), nonlinearity g and precision.  Precomputes the per-axis Thomas
- * coefficients in FP64 on the host (rounded once to FP32 for GP_C64) and
- * allocates the plan's device buffers on the current device.
+ * omega = 0), nonlinearity g and precision.  The problem is the paper's
+ * "Nature of problem" (GP equation in 1d, 2d or 3d in a fully anisotropic
+ * harmonic trap) discretised as in "Solution method" (split-step
+ * Crank-Nicolson, imaginary- or real-time propagation).  Precomputes the
+ * per-axis Thomas coefficients of the Crank-Nicolson substeps in FP64 on the
+ * host (rounded once to FP32 for GP_C64) and allocates the plan's device
+ * buffers on the current device (the plan owns them).
  * Errors: GP_EINVAL (ndim not 1..3, n < 1, dx <= 0, dt <= 0 or non-finite, bad
  * enum, bad schedule), GP_ENOMEM, GP_EHIP (no usable device). */
 gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt,
@@ -112,15 +116,31 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
 gp_status gp_plan_destroy(gp_plan *plan);
 
 /* Advance psi (device, in place, layout above) by nsteps >= 0 SSCN steps on
- * `stream`; asynchronous.  In imaginary time psi is returned with unit norm.
- * The plan's step index advances by nsteps. */
+ * `stream`; asynchronous.  One step is the split-step Crank-Nicolson step of
+ * "Solution method" as spelled out at the top of this file; imaginary-time
+ * propagation (stationary states) returns psi with unit norm, real-time
+ * propagation (dynamics) conserves it.  The plan's step index advances by
+ * nsteps.  psi stays owned by the caller; the plan's work grid and partial
+ * buffers are used as scratch.  Errors: GP_EINVAL (NULL plan/psi, nsteps < 0),
+ * GP_EHIP (launch failure, or an earlier asynchronous fault). */
 gp_status gp_step(gp_plan *plan, void *psi, int64_t nsteps, void *stream);
 
-/* Observables of psi (device) into *out (host); synchronises `stream`.
- * Returns GP_ENONFINITE (with *out filled) if norm or energy is not finite. */
+/* Observables of psi (device) into *out (host): the energy, chemical
+ * potential and rms sizes that "Summary of revisions" lists among the
+ * programs' outputs, plus the norm and the energy's parts (definitions at
+ * gp_obs).  The trap is the one of the last step taken (step index - 1; a
+ * schedule may change it), or of step 0 before any step.  FP64 accumulation
+ * in a fixed order, so results are reproducible bit for bit.  Synchronises
+ * `stream`.  Returns GP_ENONFINITE (with *out filled) if norm or energy is not
+ * finite; GP_EINVAL for NULL arguments. */
 gp_status gp_observables(gp_plan *plan, const void *psi, gp_obs *out, void *stream);
 
-/* Set / get the index of the next step (resume, recompute segments). */
+/* Set / get the index of the next step.  Setting it resumes a run from a
+ * stored wavefunction -- the hand-over "Summary of revisions" describes, where
+ * real-time programs read a wavefunction precomputed in imaginary time (NSTP
+ * set to zero) -- or restarts a segment of the adjoint's checkpointed
+ * recomputation; the index selects the trap schedule entry of each step.
+ * GP_EINVAL for a NULL plan or a negative index. */
 gp_status gp_plan_set_step(gp_plan *plan, int64_t step);
 gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info);
 
@@ -182,24 +202,30 @@ gp_status gp_step_adjoint(gp_plan *plan, const void *states, void *lambda, int64
 
 /* A batch of `count` independent 2D problems (problem k: grid n[2k], n[2k+1]
  * (x first, each 1..1024), spacing dx[k] on both axes, step dt[k], trap
- * omega[2k], omega[2k+1], nonlinearity g[k]), all in one mode and precision.
+ * traps[k].omega[0..1] (static: a schedule gives GP_EUNSUPPORTED), nonlinearity
+ * g[k]), all in one mode and precision -- many of the paper's 2d problems
+ * ("Nature of problem") advanced by one call.
  * Each problem gets a plan as from gp_plan_create; the batch advances them
  * together (gp_batch_step), either with two launches per step (all problems'
  * x sweeps, then all y sweeps) or, in real time, with one persistent launch
  * for all steps whose wavefronts take (step, phase, problem, tile) items from
  * a device queue and wait on per-problem completion counters.
- * Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP. */
+ * Errors: GP_EINVAL, GP_ENOMEM, GP_EHIP; GP_EUNSUPPORTED for a problem the
+ * batched kernels do not run (a y sweep that needs the exact two-pass solver
+ * or a window deeper than 8 blocks of 4 points, i.e. dt/dx^2 too large, or
+ * rings beyond the device's LDS). */
 gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n /* [count][2] */,
                           const double *dx, const double *dt, gp_mode mode,
-                          const double *omega /* [count][2] */, const double *g, gp_prec prec);
+                          const gp_trap *traps /* [count] */, const double *g, gp_prec prec);
 gp_status gp_batch_destroy(gp_batch *batch);
 
 /* Advance every problem k (psis[k]: device grid of problem k, layout as
  * gp_step's) by nsteps steps; the pointer array is host memory.  Imaginary
  * time renormalises every problem to unit norm.  Asynchronous, except that a
  * persistent launch synchronises `stream` to read its error flag: a bounded
- * device-side dependency wait that gave up yields GP_ETIMEOUT (the grids are
- * then not advanced consistently). */
+ * device-side dependency wait that gave up yields GP_ETIMEOUT; the grids'
+ * contents are then undefined (some items ran, some did not) and the step
+ * indices are left unchanged, so the caller must reload them. */
 gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream);
 
 /* Time candidate configurations -- persistent or phased launch, x lines per
@@ -212,6 +238,9 @@ gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void
  * Synchronises `stream`. */
 gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *stream);
 
+/* gp_batch_autotune on the null stream (the boundary's tuning call). */
+gp_status gp_autotune(gp_batch *batch, const char *cache_path);
+
 /* Bound, in polls (each a short sleep), of one dependency wait in the
  * persistent launch (default 2^22, about 0.3 s): for callers that must bound a
  * stalled launch, and for exercising the GP_ETIMEOUT path. */
@@ -222,7 +251,8 @@ gp_status gp_batch_set_wait_limit(gp_batch *batch, uint32_t polls);
 gp_status gp_batch_get_config(const gp_batch *batch, int *persistent, int *lines, int *ysegs, int *grid);
 gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ysegs, int grid);
 
-/* Observables of problem k of a batch (as gp_observables). */
+/* Observables of problem k of a batch (as gp_observables).  GP_EINVAL for a
+ * NULL batch or k outside 0..count-1. */
 gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream);
 
 /* ---------------------------------------------------- measurement aids */

@@ -75,7 +75,8 @@ def lib():
             "gp_thomas_table": [i64, d, d, i32, i32, i32, c_dp, c_dp, ctypes.POINTER(ctypes.c_int), c_dp],
             "gp_step_adjoint": [vp, vp, vp, i64, i64, vp, vp, vp],
             "gp_step_record": [vp, vp, i64, vp, vp],
-            "gp_batch_create": [pp, i32, c_i64p, c_dp, c_dp, i32, c_dp, c_dp, i32],
+            "gp_batch_create": [pp, i32, c_i64p, c_dp, c_dp, i32, ctypes.POINTER(GpTrap), c_dp, i32],
+            "gp_autotune": [vp, ctypes.c_char_p],
             "gp_batch_destroy": [vp],
             "gp_batch_step": [vp, pp, i64, vp],
             "gp_batch_autotune": [vp, ctypes.c_char_p, vp],
@@ -272,12 +273,15 @@ class Batch:
         n = np.ascontiguousarray(np.array(self.sizes, dtype=np.int64).reshape(-1))
         dxa = np.ascontiguousarray(np.broadcast_to(np.asarray(dx, dtype=np.float64), (self.count,)))
         dta = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.count,)))
-        om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(self.count, 2).reshape(-1))
+        om = np.asarray(omega, dtype=np.float64).reshape(self.count, 2)
+        traps = (GpTrap * self.count)()
+        for k in range(self.count):
+            traps[k].omega[0], traps[k].omega[1] = float(om[k, 0]), float(om[k, 1])
         ga = np.ascontiguousarray(np.broadcast_to(np.asarray(g, dtype=np.float64), (self.count,)))
         h = ctypes.c_void_p()
         check(L.gp_batch_create(ctypes.byref(h), self.count, n.ctypes.data_as(c_i64p), dxa.ctypes.data_as(c_dp),
-                                dta.ctypes.data_as(c_dp), int(mode), om.ctypes.data_as(c_dp),
-                                ga.ctypes.data_as(c_dp), self.prec), "gp_batch_create")
+                                dta.ctypes.data_as(c_dp), int(mode), traps, ga.ctypes.data_as(c_dp),
+                                self.prec), "gp_batch_create")
         self._h = h
 
     def shape(self, k):

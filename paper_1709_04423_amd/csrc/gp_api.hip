@@ -165,6 +165,18 @@ static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
     if (A.npad < A.n + 1) A.npad = A.n + 1;
 }
 
+AxisPlan preview_axis(int64_t n, int64_t nlines, double dx, double dt, gp_mode mode, gp_prec prec, int B, bool tile)
+{
+    AxisPlan A;
+    A.n = n;
+    A.nlines = nlines;
+    A.r = dt / (4.0 * dx * dx);
+    std::vector<std::complex<long double>> c;
+    thomas_c(A.n, A.r, mode, c, A.rho);
+    choose_window(A, prec, B, tile);
+    return A;
+}
+
 // x sweep with one wavefront per line: Q = points per lane (power of two,
 // n <= 64 Q <= 64 kXMaxQ), scan steps S = smallest with Q 2^S > Kmin (full
 // scan, S = 6, when that is not below 64 lanes), and the first point from

@@ -136,7 +136,7 @@ __device__ __forceinline__ void run_y_item(const SweepParams &P0, const BatchIte
     case 6: window_run<R, MODE, FLAGS, kStrided, 6, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
     case 7: window_run<R, MODE, FLAGS, kStrided, 7, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
     case 8: window_run<R, MODE, FLAGS, kStrided, 8, 4>(P, src, dst, tab, nullptr, lds, it.first, it.seg, it.segs, part); break;
-    default: break;
+    default: break;  // excluded when the batch is created (batch_supports)
     }
 }
 
@@ -462,6 +462,34 @@ static gp_status check_error_flag(gp_batch *b, hipStream_t s)
     return GP_OK;
 }
 
+// The batched kernels run the x sweep with the scan solver and the y sweep with
+// the windowed solver of depth 1..8 blocks of 4 points, four wavefronts per
+// workgroup each holding its ring (or x transpose buffer) in LDS.  A problem
+// outside that (an exact two-pass y solve, a deeper window, a ring set too
+// large for the device's LDS) is rejected when the batch is created.
+// The y-sweep half of the check runs on the host before any HIP call.
+static gp_status batch_y_supported(const AxisPlan &Y)
+{
+    if (Y.K < 0 || Y.B != 4 || Y.D < 1 || Y.D > 8)
+        return set_error("batched y sweep needs a windowed solve of 1..8 blocks (dt/dx^2 too large)"),
+               GP_EUNSUPPORTED;
+    return GP_OK;
+}
+
+static gp_status batch_supports(const gp_plan *p, int max_lds)
+{
+    const AxisPlan &X = p->ax[0], &Y = p->ax[1];
+    if (X.xq < 1 || X.xq > kXMaxQ) return set_error("batched x sweep needs 1 <= nx <= 1024"), GP_EUNSUPPORTED;
+    const gp_status st = batch_y_supported(Y);
+    if (st != GP_OK) return st;
+    const size_t ring = p->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(Y.L)
+                                           : window_lds_bytes<float, kStrided, 4>(Y.L);
+    const size_t xl = p->prec == GP_C128 ? x_lds_bytes<double>(X.xq) : x_lds_bytes<float>(X.xq);
+    if (max_lds > 0 && (int64_t)kBatchWaves * (int64_t)std::max(ring, xl) > (int64_t)max_lds)
+        return set_error("batched sweep's LDS (4 wavefronts' rings) exceeds the device limit"), GP_EUNSUPPORTED;
+    return GP_OK;
+}
+
 static std::string cache_key(const gp_batch *b)
 {
     std::vector<std::string> sizes;
@@ -480,25 +508,40 @@ using namespace gp;
 extern "C" {
 
 gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n, const double *dx, const double *dt,
-                          gp_mode mode, const double *omega, const double *g, gp_prec prec)
+                          gp_mode mode, const gp_trap *traps, const double *g, gp_prec prec)
 {
-    if (!out || count < 1 || !n || !dx || !dt || !omega || !g) return set_error("bad argument"), GP_EINVAL;
+    if (!out || count < 1 || !n || !dx || !dt || !traps || !g) return set_error("bad argument"), GP_EINVAL;
     *out = nullptr;
     if (mode != GP_IMAG && mode != GP_REAL) return set_error("bad mode"), GP_EINVAL;
     if (prec != GP_C128 && prec != GP_C64) return set_error("bad precision"), GP_EINVAL;
-    for (int k = 0; k < count; ++k)
+    for (int k = 0; k < count; ++k) {
         if (n[2 * k] < 1 || n[2 * k + 1] < 1 || n[2 * k] > 64 * kXMaxQ)
             return set_error("batch problems need 1 <= n <= 1024 per axis"), GP_EINVAL;
+        if (!(dx[k] > 0.0) || !(dt[k] > 0.0) || !std::isfinite(dx[k]) || !std::isfinite(dt[k]))
+            return set_error("dx and dt must be finite and > 0"), GP_EINVAL;
+        if (traps[k].sched_len != 0)
+            return set_error("batched problems take static traps (no schedule)"), GP_EUNSUPPORTED;
+        const gp_status st =
+            batch_y_supported(preview_axis(n[2 * k + 1], n[2 * k], dx[k], dt[k], mode, prec, 4, false));
+        if (st != GP_OK) return st;
+    }
     gp_batch *b = new (std::nothrow) gp_batch();
     if (!b) return set_error("host allocation failed"), GP_ENOMEM;
     b->count = count;
     b->mode = mode;
     b->prec = prec;
-    hipGetDevice(&b->device);
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        gp_batch_destroy(b);
+        return hip_fail(e, "hipGetDevice");
+    }
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
+        max_lds = 0;
     for (int k = 0; k < count; ++k) {
         gp_trap trap{};
-        trap.omega[0] = omega[2 * k];
-        trap.omega[1] = omega[2 * k + 1];
+        trap.omega[0] = traps[k].omega[0];
+        trap.omega[1] = traps[k].omega[1];
         const double dxs[2] = {dx[k], dx[k]};
         gp_plan *p = nullptr;
         gp_status st = gp_plan_create(&p, 2, n + 2 * k, dxs, dt[k], mode, &trap, g[k], prec);
@@ -508,6 +551,11 @@ gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n, const dou
         }
         b->plans.push_back(p);
         b->qmax = std::max(b->qmax, p->ax[0].xq);
+        st = batch_supports(p, max_lds);
+        if (st != GP_OK) {
+            gp_batch_destroy(b);
+            return st;
+        }
     }
     *out = b;
     return GP_OK;
@@ -536,8 +584,10 @@ gp_status gp_batch_step(gp_batch *b, void *const *psis, int64_t nsteps, void *st
     const int64_t step0 = b->plans[0]->step;
     e = run_batch(b, step0, nsteps, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    st = check_error_flag(b, s);
+    if (st != GP_OK) return st;  // the grids are not advanced consistently: step indices stay put
     for (gp_plan *p : b->plans) p->step += nsteps;
-    return check_error_flag(b, s);
+    return GP_OK;
 }
 
 gp_status gp_batch_observables(gp_batch *b, int k, const void *psi, gp_obs *out, void *stream)
@@ -637,6 +687,8 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
     }
     return GP_OK;
 }
+
+gp_status gp_autotune(gp_batch *b, const char *cache_path) { return gp_batch_autotune(b, cache_path, nullptr); }
 
 gp_status gp_batch_set_wait_limit(gp_batch *b, uint32_t polls)
 {

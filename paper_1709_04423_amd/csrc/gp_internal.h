@@ -181,9 +181,15 @@ hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s)
 // Number of workgroups a sweep along `axis` launches.
 int64_t sweep_groups(const gp_plan *p, int axis);
 int64_t obs_groups(const gp_plan *p);
+int64_t obs_groups_of(int ndim, const int64_t *n);  // workgroups of the observables kernel for a grid
 constexpr int kObsFields = 10;
 constexpr int kObsThreads = 256;
 
 void omega_at_step(const gp_plan *p, int64_t step, double w[3]);
+
+// Window choice of one axis exactly as gp_plan_create makes it (host only, no
+// device tables): for checks that must run before any HIP call.
+AxisPlan preview_axis(int64_t n, int64_t nlines, double dx, double dt, gp_mode mode, gp_prec prec, int B,
+                      bool tile);
 
 }  // namespace gp

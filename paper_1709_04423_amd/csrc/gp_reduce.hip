@@ -59,6 +59,8 @@ struct ObsParams {
     int64_t nx, ny, nz;
     int ndim;
     double x0[3], dx[3], hw2[3];
+    int64_t cx, cy, cz;  // tiles along x (64 columns), y (kObsTileRows rows), z (zc planes)
+    int64_t zc;
 };
 
 __device__ __forceinline__ double abs2d(double re, double im) { return re * re + im * im; }
@@ -80,57 +82,81 @@ __device__ void block_reduce_fields(double *acc, double *out)
     }
 }
 
-// One thread per (i, j) column, marching along z.  Fields:
-// 0 sum|u|^2, 1 sum V|u|^2, 2 sum|u|^4, 3-5 sum x_a^2|u|^2, 6-8 kinetic sums per axis.
+constexpr int kObsRows = 4;                       // rows per wavefront
+constexpr int kObsTileRows = kObsRows * (kObsThreads / kLanes);  // rows per workgroup
+
+// Observables of one tile: 64 columns (one per lane) by kObsTileRows rows (the
+// workgroup's wavefronts stacked along y), marching through zc planes.  The
+// kinetic sums use backward differences: point p adds |u_p - u_{p-1}|^2 along
+// each axis (u_{-1} = 0) and the last point of a line also adds |u_{N-1}|^2 --
+// the same terms as the forward differences over i = -1..N-1.  The previous
+// value along z stays in registers and the one along x comes from the next
+// lower lane, so each point is read once; only the tile's edges (the column
+// left of it, the row below it, the plane before it) are read again.
+// Fields: 0 sum|u|^2, 1 sum V|u|^2, 2 sum|u|^4, 3-5 sum x_a^2|u|^2, 6-8 kinetic sums per axis.
 template <typename R>
-__global__ __launch_bounds__(256) void k_observables(const typename VT<R>::V *__restrict__ psi,
-                                                     ObsParams O, double *__restrict__ part)
+__global__ __launch_bounds__(kObsThreads) void k_observables(const typename VT<R>::V *__restrict__ psi,
+                                                             ObsParams O, double *__restrict__ part)
 {
+    using V = typename VT<R>::V;
+    const int lane = threadIdx.x & (kLanes - 1), w = threadIdx.x / kLanes;
+    int64_t b = blockIdx.x;
+    const int64_t bx = b % O.cx;
+    b /= O.cx;
+    const int64_t by = b % O.cy, bz = b / O.cy;
+    const int64_t i = bx * kLanes + lane;
+    const int64_t j0 = by * kObsTileRows + (int64_t)w * kObsRows;
+    const int64_t k0 = bz * O.zc, k1 = min(k0 + O.zc, O.nz);
+    const int64_t plane = O.nx * O.ny;
+    const bool xin = i < O.nx;
+    const double x = ((double)i + O.x0[0]) * O.dx[0];
     double acc[kObsFields];
     for (int f = 0; f < kObsFields; ++f) acc[f] = 0.0;
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col < O.nx * O.ny) {
-        const int64_t i = col % O.nx, j = col / O.nx;
-        const double x = ((double)i + O.x0[0]) * O.dx[0];
-        const double y = ((double)j + O.x0[1]) * O.dx[1];
-        const int64_t plane = O.nx * O.ny;
-        double pr = 0.0, pi = 0.0;  // previous value along z (ghost 0 before k = 0)
-        for (int64_t k = 0; k < O.nz; ++k) {
-            const double z = ((double)k + O.x0[2]) * O.dx[2];
-            const int64_t at = col + k * plane;
-            const typename VT<R>::V u = psi[at];
-            const double ur = u.x, ui = u.y;
-            const double d = abs2d(ur, ui);
-            acc[0] += d;
-            acc[1] += (O.hw2[0] * x * x + O.hw2[1] * y * y + O.hw2[2] * z * z) * d;
-            acc[2] += d * d;
-            acc[3] += x * x * d;
-            acc[4] += y * y * d;
-            acc[5] += z * z * d;
-            // x: |u_{i+1} - u_i|^2 with u_nx = 0, plus |u_0|^2 for the i = -1 term
-            {
-                double nr = 0.0, ni = 0.0;
-                if (i + 1 < O.nx) {
-                    const typename VT<R>::V w = psi[at + 1];
-                    nr = w.x;
-                    ni = w.y;
-                }
-                acc[6] += abs2d(nr - ur, ni - ui) + (i == 0 ? d : 0.0);
-            }
-            if (O.ndim >= 2) {
-                double nr = 0.0, ni = 0.0;
-                if (j + 1 < O.ny) {
-                    const typename VT<R>::V w = psi[at + O.nx];
-                    nr = w.x;
-                    ni = w.y;
-                }
-                acc[7] += abs2d(nr - ur, ni - ui) + (j == 0 ? d : 0.0);
-            }
-            if (O.ndim >= 3) acc[8] += abs2d(ur - pr, ui - pi);
-            pr = ur;
-            pi = ui;
+    auto ld = [&](int64_t ii, int64_t jj, int64_t kk, bool ok) -> V {
+        V v;
+        v.x = R(0);
+        v.y = R(0);
+        if (ok) v = psi[ii + O.nx * jj + plane * kk];
+        return v;
+    };
+    V zprev[kObsRows];
+#pragma unroll
+    for (int r = 0; r < kObsRows; ++r) zprev[r] = ld(i, j0 + r, k0 - 1, xin && k0 > 0 && j0 + r < O.ny);
+    for (int64_t k = k0; k < k1; ++k) {
+        const double z = ((double)k + O.x0[2]) * O.dx[2];
+        V u[kObsRows], left[kObsRows];
+#pragma unroll
+        for (int r = 0; r < kObsRows; ++r) u[r] = ld(i, j0 + r, k, xin && j0 + r < O.ny);
+        V below = ld(i, j0 - 1, k, xin && j0 >= 1 && j0 - 1 < O.ny);
+#pragma unroll
+        for (int r = 0; r < kObsRows; ++r) {
+            left[r].x = __shfl_up(u[r].x, 1, kLanes);
+            left[r].y = __shfl_up(u[r].y, 1, kLanes);
+            if (lane == 0) left[r] = ld(i - 1, j0 + r, k, xin && i >= 1 && j0 + r < O.ny);
         }
-        if (O.ndim >= 3) acc[8] += abs2d(pr, pi);
+#pragma unroll
+        for (int r = 0; r < kObsRows; ++r) {
+            const int64_t j = j0 + r;
+            if (xin && j < O.ny) {
+                const double y = ((double)j + O.x0[1]) * O.dx[1];
+                const double ur = u[r].x, ui = u[r].y;
+                const double d = abs2d(ur, ui);
+                acc[0] += d;
+                acc[1] += (O.hw2[0] * x * x + O.hw2[1] * y * y + O.hw2[2] * z * z) * d;
+                acc[2] += d * d;
+                acc[3] += x * x * d;
+                acc[4] += y * y * d;
+                acc[5] += z * z * d;
+                acc[6] += abs2d(ur - (double)left[r].x, ui - (double)left[r].y) + (i == O.nx - 1 ? d : 0.0);
+                if (O.ndim >= 2) {
+                    const V pv = r == 0 ? below : u[r - 1];
+                    acc[7] += abs2d(ur - (double)pv.x, ui - (double)pv.y) + (j == O.ny - 1 ? d : 0.0);
+                }
+                if (O.ndim >= 3)
+                    acc[8] += abs2d(ur - (double)zprev[r].x, ui - (double)zprev[r].y) + (k == O.nz - 1 ? d : 0.0);
+            }
+            zprev[r] = u[r];
+        }
     }
     __shared__ double out[kObsFields];
     block_reduce_fields(acc, out);
@@ -179,11 +205,30 @@ __global__ __launch_bounds__(256) void k_copy(double2 *__restrict__ dst, const d
 
 }  // namespace
 
-int64_t obs_groups(const gp_plan *p)
+// Tiling of the observables kernel: 64-column by kObsTileRows-row tiles, and the
+// z extent split into chunks of at least 8 planes until about 1024 workgroups run.
+static void obs_tiling(int ndim, const int64_t *n, int64_t &cx, int64_t &cy, int64_t &cz, int64_t &zc)
 {
-    const int64_t cols = p->n[0] * (p->ndim >= 2 ? p->n[1] : 1);
-    return (cols + kObsThreads - 1) / kObsThreads;
+    const int64_t nx = n[0], ny = ndim >= 2 ? n[1] : 1, nz = ndim >= 3 ? n[2] : 1;
+    cx = (nx + kLanes - 1) / kLanes;
+    cy = (ny + kObsTileRows - 1) / kObsTileRows;
+    const int64_t base = cx * cy;
+    int64_t want = (1024 + base - 1) / base;
+    const int64_t most = (nz + 7) / 8;
+    if (want > most) want = most;
+    if (want < 1) want = 1;
+    zc = (nz + want - 1) / want;
+    cz = (nz + zc - 1) / zc;
 }
+
+int64_t obs_groups_of(int ndim, const int64_t *n)
+{
+    int64_t cx, cy, cz, zc;
+    obs_tiling(ndim, n, cx, cy, cz, zc);
+    return cx * cy * cz;
+}
+
+int64_t obs_groups(const gp_plan *p) { return obs_groups_of(p->ndim, p->n); }
 
 hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s)
 {
@@ -217,11 +262,15 @@ hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s)
     O.ny = p->ndim >= 2 ? p->n[1] : 1;
     O.nz = p->ndim >= 3 ? p->n[2] : 1;
     O.ndim = p->ndim;
+    obs_tiling(p->ndim, p->n, O.cx, O.cy, O.cz, O.zc);
     for (int a = 0; a < 3; ++a) {
         O.x0[a] = a < p->ndim ? coord0(p->n[a]) : 0.0;
         O.dx[a] = a < p->ndim ? p->dx[a] : 0.0;
-        O.hw2[a] = a < p->ndim ? 0.5 * p->omega[a] * p->omega[a] : 0.0;
     }
+    // the trap of the last step taken (a schedule may change it), or of step 0 before any step
+    double w[3];
+    omega_at_step(p, p->step > 0 ? p->step - 1 : 0, w);
+    for (int a = 0; a < 3; ++a) O.hw2[a] = a < p->ndim ? 0.5 * w[a] * w[a] : 0.0;
     const int64_t nb = obs_groups(p);
     timing_begin(p, K_OBS, s);
     if (p->prec == GP_C128)

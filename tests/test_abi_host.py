@@ -106,6 +106,41 @@ def test_null_handles_are_rejected():
     assert L.gp_batch_step(None, None, 1, None) == binding.GP_EINVAL
 
 
+def _batch_create(sizes, dx, dt, mode, prec, traps=None):
+    L = binding.lib()
+    k = len(sizes)
+    n = (ctypes.c_int64 * (2 * k))(*[v for s in sizes for v in s])
+    dxa = (ctypes.c_double * k)(*[dx] * k)
+    dta = (ctypes.c_double * k)(*[dt] * k)
+    if traps is None:
+        traps = (binding.GpTrap * k)()
+        for t in traps:
+            t.omega[0] = t.omega[1] = 1.0
+    ga = (ctypes.c_double * k)(*[10.0] * k)
+    h = ctypes.c_void_p()
+    return L.gp_batch_create(ctypes.byref(h), k, n, dxa, dta, mode, traps, ga, prec), h
+
+
+def test_batch_create_rejects_problems_the_batched_kernels_do_not_run():
+    # dx = 0.05, dt = 5e-3 in complex128 real time: the y recurrence contracts so
+    # slowly that its window would exceed 8 blocks (or the exact solver would be
+    # needed); the batch must refuse it up front instead of skipping the y sweep
+    st, h = _batch_create([(64, 64), (128, 96)], 0.05, 5e-3, binding.GP_REAL, binding.GP_C128)
+    assert st == binding.GP_EUNSUPPORTED and not h.value
+    assert b"windowed" in binding.lib().gp_last_error()
+    # a per-problem trap schedule is not supported by the batched launch
+    traps = (binding.GpTrap * 1)()
+    arr = (ctypes.c_double * 2)(1.0, 1.1)
+    traps[0].omega_sched = ctypes.cast(arr, binding.c_dp)
+    traps[0].sched_len = 2
+    st, h = _batch_create([(64, 64)], 0.1, 1e-3, binding.GP_REAL, binding.GP_C64, traps)
+    assert st == binding.GP_EUNSUPPORTED
+    # bad spacing / time step
+    assert _batch_create([(64, 64)], 0.0, 1e-3, binding.GP_REAL, binding.GP_C64)[0] == binding.GP_EINVAL
+    assert _batch_create([(64, 64)], 0.1, float("nan"), binding.GP_REAL, binding.GP_C64)[0] == binding.GP_EINVAL
+    assert binding.lib().gp_autotune(None, None) == binding.GP_EINVAL
+
+
 def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))

@@ -111,9 +111,14 @@ def test_persistent_wait_limit_reports_timeout(gp):
     with pytest.raises(gp.GpError) as e:
         b.step(psis, 50)
     assert e.value.status == gp.GP_ETIMEOUT
-    # the batch stays usable with a normal bound
+    # the grids are undefined after a timeout and the step indices did not move:
+    # reload them, and with a normal bound the batch gives what a fresh one does
     b.set_wait_limit(1 << 22)
+    psis = [initial(k, np.complex64) for k in range(len(SIZES))]
     b.step(psis, 2)
+    _, ref = run_batch(gp, 1, gp.GP_C64, dict(persistent=1, grid=1024, lines=1, ysegs=8), steps=2)
+    for k in range(len(SIZES)):
+        assert np.array_equal(psis[k].cpu().numpy(), ref[k]), k
 
 
 def test_autotune_and_cache(gp, tmp_path):
