@@ -38,13 +38,28 @@ def _compile(src: str, extra=(), objdir=OBJDIR) -> str:
     return obj
 
 
-def build(verbose: bool = False, extra=(), lib=None, objdir=None) -> str:
+def _stale(src: str, objdir: str) -> bool:
+    """Whether src's object is missing or older than src or any header."""
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [src] + headers)
+
+
+def build(verbose: bool = False, extra=(), lib=None, objdir=None, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental=True, those whose object is
+    older than the source or a header) and link libgp.so."""
     objdir = objdir or OBJDIR
     lib = lib or LIB
     os.makedirs(objdir, exist_ok=True)
     srcs = sources()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda f: _compile(f, extra, objdir), srcs))
+    todo = [f for f in srcs if _stale(f, objdir)] if incremental else srcs
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(8, len(todo)))) as ex:
+        list(ex.map(lambda f: _compile(f, extra, objdir), todo))
+    objs = [os.path.join(objdir, os.path.basename(f) + ".o") for f in srcs]
     tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,5 +72,5 @@ def build(verbose: bool = False, extra=(), lib=None, objdir=None) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)
