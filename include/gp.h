@@ -255,6 +255,27 @@ gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ys
  * NULL batch or k outside 0..count-1. */
 gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream);
 
+/* --------------------------------------- observables without allocation */
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * observables of gp_observables for a grid described by its arguments instead
+ * of a plan (ndim, n[], dx[] as gp_plan_create; omega[ndim] the trap, NULL for
+ * none; psi device, layout above; *out host).  Same kernels and summation
+ * order as gp_observables, so the results are bitwise those of a plan of that
+ * grid and trap.  The partial sums live in one static device array of the
+ * library per device ((GP_OBS_NOALLOC_MAX_GROUPS + 1) x 10 FP64, about
+ * 640 KiB), looked up on the first call on a device; the call allocates
+ * nothing.  Every call on a device shares that array, so calls that overlap on
+ * one device (other threads, other streams) race.  Synchronises `stream`.
+ * Errors: GP_EINVAL (bad argument), GP_EUNSUPPORTED (grid needs more than
+ * GP_OBS_NOALLOC_MAX_GROUPS workgroups: ceil(nx/64) ceil(ny/16) above it, e.g.
+ * a 2D grid beyond 2048 x 4096 or a 1D grid beyond 524288 points), GP_EHIP,
+ * GP_ENONFINITE. */
+#define GP_OBS_NOALLOC_MAX_GROUPS 8192
+gp_status gp_observables_noalloc(int ndim, const int64_t *n, const double *dx, const double *omega, double g,
+                                 gp_prec prec, const void *psi, gp_obs *out, void *stream);
+
 /* ---------------------------------------------------- measurement aids */
 
 /* Per-kernel timing with HIP events recorded on the plan's launch stream around

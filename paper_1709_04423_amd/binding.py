@@ -88,6 +88,7 @@ def lib():
             "gp_plan_timing_enable": [vp, i64],
             "gp_plan_timing_read": [vp, c_i64p, c_dp],
             "gp_copy_probe": [vp, vp, i64, vp],
+            "gp_observables_noalloc": [i32, c_i64p, c_dp, c_dp, d, i32, vp, ctypes.POINTER(GpObs), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -343,6 +344,22 @@ def thomas_table(n: int, dx: float, dt: float, mode: int, prec: int = GP_C128, a
                                 c.ctypes.data_as(c_dp), beta.ctypes.data_as(c_dp), ctypes.byref(K),
                                 ctypes.byref(rho)), "gp_thomas_table")
     return c.view(np.complex128), beta.view(np.complex128), K.value, rho.value
+
+
+def observables_noalloc(psi, dx, omega=None, g: float = 0.0, stream=None) -> dict:
+    """gp_observables_noalloc: observables of psi (x-first spacings dx, trap omega)
+    without a plan; the library allocates nothing (static partial-sum array)."""
+    n = tuple(int(v) for v in psi.shape[::-1])
+    nd = len(n)
+    prec = _prec_of(psi.dtype)
+    _check_psi(psi, psi.shape, prec)
+    dxs = [float(v) for v in (dx if hasattr(dx, "__len__") else [dx] * nd)]
+    om = None if omega is None else (ctypes.c_double * nd)(*[float(v) for v in omega])
+    o = GpObs()
+    check(lib().gp_observables_noalloc(nd, (ctypes.c_int64 * nd)(*n), (ctypes.c_double * nd)(*dxs), om, float(g),
+                                       prec, ctypes.c_void_p(psi.data_ptr()), ctypes.byref(o), _stream_handle(stream)),
+          "gp_observables_noalloc")
+    return o.as_dict()
 
 
 def copy_probe(dst, src, stream=None):

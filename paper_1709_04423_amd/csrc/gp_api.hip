@@ -623,15 +623,7 @@ gp_status gp_observables(gp_plan *p, const void *psi, gp_obs *out, void *stream)
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(observables)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    const double dv = p->dV;
-    out->norm = dv * f[0];
-    out->epot = dv * f[1];
-    out->eint = 0.5 * p->g * dv * f[2];
-    out->ekin = 0.0;
-    for (int a = 0; a < p->ndim; ++a) out->ekin += 0.5 * dv * f[6 + a] / (p->dx[a] * p->dx[a]);
-    out->energy = out->ekin + out->epot + out->eint;
-    out->mu = out->ekin + out->epot + 2.0 * out->eint;
-    for (int a = 0; a < 3; ++a) out->rms[a] = a < p->ndim ? std::sqrt(dv * f[3 + a] / out->norm) : 0.0;
+    obs_from_sums(f, p->ndim, p->dx, p->g, out);
     if (!std::isfinite(out->norm) || !std::isfinite(out->energy)) {
         set_error("non-finite norm or energy");
         return GP_ENONFINITE;

@@ -174,6 +174,8 @@ int xy_choose_segments(const gp_plan *p, int64_t max_lds);  // 0: the shape is n
 constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
+// Observables from the kObsFields final sums (norm, E parts, mu, rms) of a grid.
+void obs_from_sums(const double *f, int ndim, const double *dx, double g, gp_obs *out);
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,
                              double *dg, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s);

@@ -2,6 +2,10 @@
 // observables (FP64 accumulation, deterministic fixed-order block sums),
 // the per-step reduction of the adjoint's gradient partials, and a plain copy
 // kernel used to calibrate bandwidth and memory counters.
+#include <cmath>
+#include <mutex>
+#include <string>
+
 #include "gp_internal.h"
 
 namespace gp {
@@ -255,37 +259,60 @@ hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s)
+// The observables kernels of a grid into `part` (nb = obs_groups_of partial rows
+// of kObsFields, then the final sums in row nb).  Shared by the plan's entry
+// point and the plan-free one.
+static hipError_t launch_obs_kernels(int ndim, const int64_t *n, const double *dx, const double *omega, gp_prec prec,
+                                     const void *psi, double *part, gp_plan *timed, hipStream_t s)
 {
     ObsParams O{};
-    O.nx = p->n[0];
-    O.ny = p->ndim >= 2 ? p->n[1] : 1;
-    O.nz = p->ndim >= 3 ? p->n[2] : 1;
-    O.ndim = p->ndim;
-    obs_tiling(p->ndim, p->n, O.cx, O.cy, O.cz, O.zc);
+    O.nx = n[0];
+    O.ny = ndim >= 2 ? n[1] : 1;
+    O.nz = ndim >= 3 ? n[2] : 1;
+    O.ndim = ndim;
+    obs_tiling(ndim, n, O.cx, O.cy, O.cz, O.zc);
     for (int a = 0; a < 3; ++a) {
-        O.x0[a] = a < p->ndim ? coord0(p->n[a]) : 0.0;
-        O.dx[a] = a < p->ndim ? p->dx[a] : 0.0;
+        O.x0[a] = a < ndim ? coord0(n[a]) : 0.0;
+        O.dx[a] = a < ndim ? dx[a] : 0.0;
+        O.hw2[a] = a < ndim ? 0.5 * omega[a] * omega[a] : 0.0;
     }
+    const int64_t nb = obs_groups_of(ndim, n);
+    if (timed) timing_begin(timed, K_OBS, s);
+    if (prec == GP_C128)
+        hipLaunchKernelGGL(k_observables<double>, dim3((unsigned)nb), dim3(kObsThreads), 0, s,
+                           (const double2 *)psi, O, part);
+    else
+        hipLaunchKernelGGL(k_observables<float>, dim3((unsigned)nb), dim3(kObsThreads), 0, s,
+                           (const float2 *)psi, O, part);
+    if (timed) timing_end(timed, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (timed) timing_begin(timed, K_OBS_FINAL, s);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, part, nb, part + nb * kObsFields);
+    if (timed) timing_end(timed, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s)
+{
     // the trap of the last step taken (a schedule may change it), or of step 0 before any step
     double w[3];
     omega_at_step(p, p->step > 0 ? p->step - 1 : 0, w);
-    for (int a = 0; a < 3; ++a) O.hw2[a] = a < p->ndim ? 0.5 * w[a] * w[a] : 0.0;
-    const int64_t nb = obs_groups(p);
-    timing_begin(p, K_OBS, s);
-    if (p->prec == GP_C128)
-        hipLaunchKernelGGL(k_observables<double>, dim3((unsigned)nb), dim3(kObsThreads), 0, s,
-                           (const double2 *)psi, O, p->d_obs);
-    else
-        hipLaunchKernelGGL(k_observables<float>, dim3((unsigned)nb), dim3(kObsThreads), 0, s,
-                           (const float2 *)psi, O, p->d_obs);
-    timing_end(p, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    timing_begin(p, K_OBS_FINAL, s);
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, p->d_obs, nb, p->d_obs + nb * kObsFields);
-    timing_end(p, s);
-    return hipGetLastError();
+    return launch_obs_kernels(p->ndim, p->n, p->dx, w, p->prec, psi, p->d_obs, p, s);
+}
+
+void obs_from_sums(const double *f, int ndim, const double *dx, double g, gp_obs *out)
+{
+    double dv = 1.0;
+    for (int a = 0; a < ndim; ++a) dv *= dx[a];
+    out->norm = dv * f[0];
+    out->epot = dv * f[1];
+    out->eint = 0.5 * g * dv * f[2];
+    out->ekin = 0.0;
+    for (int a = 0; a < ndim; ++a) out->ekin += 0.5 * dv * f[6 + a] / (dx[a] * dx[a]);
+    out->energy = out->ekin + out->epot + out->eint;
+    out->mu = out->ekin + out->epot + 2.0 * out->eint;
+    for (int a = 0; a < 3; ++a) out->rms[a] = a < ndim ? std::sqrt(dv * f[3 + a] / out->norm) : 0.0;
 }
 
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double coeff, double *dsched_k, double *dg,
@@ -309,3 +336,85 @@ hipError_t launch_copy(void *dst, const void *src, int64_t bytes, hipStream_t s)
 }
 
 }  // namespace gp
+
+// ------------------------------------------------------------ observables without allocation
+
+namespace gp {
+
+namespace {
+
+// Partial sums of gp_observables_noalloc: GP_OBS_NOALLOC_MAX_GROUPS rows of
+// kObsFields FP64 values and the row of final sums, in a static device array
+// (one copy on every device the library runs on, held until the process ends).
+constexpr int64_t kObsScratchGroups = GP_OBS_NOALLOC_MAX_GROUPS;
+__device__ __align__(256) double scratch[(kObsScratchGroups + 1) * kObsFields];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` per device (host copy of the symbol is not it)
+
+// The array's device address on the current device, looked up once per device.
+gp_status scratch_address(int dev, double **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(observables scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GP_OK;
+}
+
+}  // namespace
+
+}  // namespace gp
+
+extern "C" gp_status gp_observables_noalloc(int ndim, const int64_t *n, const double *dx, const double *omega,
+                                            double g, gp_prec prec, const void *psi, gp_obs *out, void *stream)
+{
+    using namespace gp;
+    if (ndim < 1 || ndim > 3 || !n || !dx || !psi || !out) return set_error("bad argument"), GP_EINVAL;
+    if (prec != GP_C128 && prec != GP_C64) return set_error("bad precision"), GP_EINVAL;
+    if (!std::isfinite(g)) return set_error("g must be finite"), GP_EINVAL;
+    double w[3] = {0.0, 0.0, 0.0};
+    int64_t npts = 1;
+    for (int a = 0; a < ndim; ++a) {
+        if (n[a] < 1 || n[a] > ((int64_t)1 << 31) || npts > ((int64_t)1 << 40) / n[a])
+            return set_error("grid size must be 1..2^31 per axis and 2^40 in all"), GP_EINVAL;
+        if (!(dx[a] > 0.0) || !std::isfinite(dx[a])) return set_error("dx must be finite and > 0"), GP_EINVAL;
+        if (omega) {
+            if (!std::isfinite(omega[a])) return set_error("omega must be finite"), GP_EINVAL;
+            w[a] = omega[a];
+        }
+        npts *= n[a];
+    }
+    const int64_t nb = obs_groups_of(ndim, n);
+    if (nb > kObsScratchGroups)
+        return set_error("grid too large for the static observables scratch (ceil(nx/64) ceil(ny/16) > " +
+                         std::to_string(kObsScratchGroups) + ")"),
+               GP_EUNSUPPORTED;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error("device index beyond the scratch table"), GP_EUNSUPPORTED;
+    double *part = nullptr;
+    gp_status st = scratch_address(dev, &part);
+    if (st != GP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    e = launch_obs_kernels(ndim, n, dx, w, prec, psi, part, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "observables launch");
+    double f[kObsFields];
+    e = hipMemcpyAsync(f, part + nb * kObsFields, sizeof(f), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(observables)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    obs_from_sums(f, ndim, dx, g, out);
+    if (!std::isfinite(out->norm) || !std::isfinite(out->energy)) {
+        set_error("non-finite norm or energy");
+        return GP_ENONFINITE;
+    }
+    return GP_OK;
+}
+

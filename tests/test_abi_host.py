@@ -104,6 +104,17 @@ def test_null_handles_are_rejected():
     h = ctypes.c_void_p()
     assert L.gp_batch_create(ctypes.byref(h), 0, None, None, None, 1, None, None, 1) == binding.GP_EINVAL
     assert L.gp_batch_step(None, None, 1, None) == binding.GP_EINVAL
+    # the no-allocation observables check their arguments before any HIP call
+    one = (ctypes.c_int64 * 1)(8)
+    dx = (ctypes.c_double * 1)(0.1)
+    assert L.gp_observables_noalloc(0, one, dx, None, 0.0, 0, None, ctypes.byref(obs), None) == binding.GP_EINVAL
+    assert L.gp_observables_noalloc(1, one, dx, None, 0.0, 0, None, ctypes.byref(obs), None) == binding.GP_EINVAL
+    bad = (ctypes.c_double * 1)(-0.1)
+    assert L.gp_observables_noalloc(1, one, bad, None, 0.0, 0, ctypes.c_void_p(16), ctypes.byref(obs),
+                                    None) == binding.GP_EINVAL
+    big = (ctypes.c_int64 * 1)(8192 * 64 + 1)
+    assert L.gp_observables_noalloc(1, big, dx, None, 0.0, 0, ctypes.c_void_p(16), ctypes.byref(obs),
+                                    None) == binding.GP_EUNSUPPORTED
 
 
 def _batch_create(sizes, dx, dt, mode, prec, traps=None):
