@@ -67,8 +67,11 @@ def _load():
         lib.oracle_observables.argtypes = [c_int, i64p, dp, dp, c_d, dp, dp]
         lib.oracle_adjoint_step.argtypes = [c_int, i64p, dp, c_d, dp, dp, c_i64, c_int, c_d,
                                             c_i64, dp, dp, dp, dp]
+        lib.oracle_radial_step.argtypes = [c_int, i64p, dp, c_d, c_int, dp, c_d, c_i64, dp]
+        lib.oracle_radial_observables.argtypes = [c_int, i64p, dp, dp, c_d, dp, dp]
         for f in (lib.oracle_thomas, lib.oracle_cn_axis, lib.oracle_nonlinear, lib.oracle_step,
-                  lib.oracle_observables, lib.oracle_adjoint_step):
+                  lib.oracle_observables, lib.oracle_adjoint_step, lib.oracle_radial_step,
+                  lib.oracle_radial_observables):
             f.restype = c_int
         _lib = lib
     return _lib
@@ -215,3 +218,52 @@ def gradient(psi0, psi_target, dx, dt, omega, g, sched, sched_axis=0):
         dsched[k] = dth * sched[k]
         dg += dgk
     return loss, dsched, dg, lam
+
+
+# ------------------------------------------------------------------ symmetric traps
+# The circularly symmetric 2D, spherically symmetric 3D and axially symmetric 3D
+# problems of "Nature of problem", on the cell-centred radial grid r_i = (i + 1/2) dr
+# with the finite-volume radial Laplacian described in gp_oracle.c.
+
+CIRCULAR, SPHERICAL, AXIAL = 1, 2, 3
+RADIAL_FIELDS = ("norm", "mu", "energy", "ekin", "epot", "eint", "rms_r", "rms_z")
+
+
+def _radial_args(psi, geom, dx):
+    if geom == AXIAL:
+        if psi.ndim != 2:
+            raise ValueError("axial grids are (Nz, Nrho)")
+        n = np.array([psi.shape[1], psi.shape[0]], dtype=np.int64)
+        dxa = np.array(np.broadcast_to(np.asarray(dx, dtype=np.float64), (2,)), dtype=np.float64)
+    else:
+        if psi.ndim != 1:
+            raise ValueError("radial grids are (Nr,)")
+        n = np.array([psi.shape[0]], dtype=np.int64)
+        dxa = np.array([float(np.ravel(dx)[0])], dtype=np.float64)
+    return n, dxa
+
+
+def radial_step(psi, geom, dx, dt, mode, omega, g, nsteps=1):
+    """nsteps SSCN steps of a symmetric-trap problem (omega = (w_r,) or (w_rho, w_z))."""
+    lib = _load()
+    out = _c128(psi)
+    n, dxa = _radial_args(out, geom, dx)
+    w = np.zeros(2)
+    w[:len(np.ravel(omega))] = np.ravel(omega)
+    _check(lib.oracle_radial_step(geom, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dxa), dt, mode,
+                                  _dp(w), g, nsteps, _dp(out)), "radial_step")
+    return out
+
+
+def radial_observables(psi, geom, dx, omega, g) -> dict:
+    """norm, mu, energy, ekin, epot, eint, rms_r (rho) and rms_z (axial) of psi."""
+    lib = _load()
+    a = np.ascontiguousarray(psi, dtype=np.complex128)
+    n, dxa = _radial_args(a, geom, dx)
+    w = np.zeros(2)
+    w[:len(np.ravel(omega))] = np.ravel(omega)
+    out = np.zeros(9)
+    _check(lib.oracle_radial_observables(geom, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dxa), _dp(w),
+                                         g, _dp(a), _dp(out)), "radial_observables")
+    return dict(zip(RADIAL_FIELDS, out[:8].tolist()))
+

@@ -432,3 +432,221 @@ int oracle_adjoint_step(int ndim, const int64_t *n, const double *dx, double dt,
     *dg = dt * ksum_value(&sum_wd);
     return 0;
 }
+
+/* ====================================================== symmetric traps ==
+ * The paper's programs also solve the equation for three trap symmetries that
+ * reduce the dimension ("Nature of problem"): circularly symmetric 2D traps
+ * (psi(r)), spherically symmetric 3D traps (psi(r)) and axially symmetric 3D
+ * traps (psi(rho, z)).  The discretisation is left to the earlier papers, so
+ * the reading used here (and by the GPU path) is:
+ *  - cell-centred radial grid r_i = (i + 1/2) dr, i = 0..N-1, zero ghost at
+ *    i = N (the outer wall); no boundary condition is needed at r = 0 because
+ *    the face there has zero area;
+ *  - finite-volume radial Laplacian in d dimensions (d = 2 circular and axial,
+ *    3 spherical): with face areas a_{i+1/2} = ((i+1) dr)^(d-1) and cell
+ *    weights w_i = [ r_{i+1/2}^d - r_{i-1/2}^d ] / (d dr) (the exact cell volume
+ *    over dr: r_i in 2D, r_i^2 + dr^2/12 in 3D),
+ *        (L psi)_i = [ a_{i+1/2} (psi_{i+1} - psi_i) - a_{i-1/2} (psi_i - psi_{i-1}) ] / (w_i dr^2),
+ *    which is self-adjoint in <u, v> = sum_i w_i conj(u_i) v_i: with
+ *    S = -1/2 W L (symmetric tridiagonal) the CN substep solves
+ *        (W + i tau S) psi' = (W - i tau S) psi,   tau = dt/2 (real time),
+ *        (W + tau S) psi' = (W - tau S) psi                  (imaginary time),
+ *    so real-time substeps conserve sum w |psi|^2 exactly;
+ *  - axial: the rho substep as above (d = 2), then a Cartesian CN substep
+ *    along z with the z grid of the Cartesian programs; the two commute;
+ *  - norm = m sum_i w_i |psi_i|^2 with m = 2 pi dr (circular), 4 pi dr
+ *    (spherical), 2 pi drho dz (axial); V = 1/2 (w_r^2 r^2 + w_z^2 z^2).
+ * Observables: E_kin = m/2 [ sum_faces a |psi_{i+1} - psi_i|^2 / dr^2 (the outer
+ * face to the zero ghost included) + sum w |psi_{j+1} - psi_j|^2 / dz^2 (axial,
+ * z faces as in the Cartesian programs) ], which is <psi, T psi>; E_pot, E_int,
+ * norm as weighted sums; rms[0] = sqrt(<r^2>) (rho^2 for axial), rms[1] =
+ * sqrt(<z^2>) (axial). */
+
+#define ORACLE_CIRCULAR 1
+#define ORACLE_SPHERICAL 2
+#define ORACLE_AXIAL 3
+
+static int radial_dim(int geom) { return geom == ORACLE_SPHERICAL ? 3 : 2; }
+
+static double radial_face(int64_t i, double dr, int d)  /* a_{i-1/2} = (i dr)^(d-1) */
+{
+    double r = (double)i * dr;
+    return d == 3 ? r * r : r;
+}
+
+static double radial_weight(int64_t i, double dr, int d)
+{
+    double r = ((double)i + 0.5) * dr;
+    return d == 3 ? r * r + dr * dr / 12.0 : r;
+}
+
+static double radial_measure(int geom, const double *dx)
+{
+    const double pi = 3.14159265358979323846;
+    if (geom == ORACLE_CIRCULAR) return 2.0 * pi * dx[0];
+    if (geom == ORACLE_SPHERICAL) return 4.0 * pi * dx[0];
+    return 2.0 * pi * dx[0] * dx[1];
+}
+
+/* General tridiagonal solve: sub[i] x_{i-1} + diag[i] x_i + sup[i] x_{i+1} = rhs[i]
+ * (Thomas; factors and products in long double, results rounded to double). */
+static int thomas_general(int64_t n, const cplx *sub, const cplx *diag, const cplx *sup, const cplx *rhs, cplx *x,
+                          lcplx *work)
+{
+    if (n <= 0) return 0;
+    lcplx den = diag[0];
+    work[0] = (lcplx)sup[0] / den;
+    x[0] = (cplx)((lcplx)rhs[0] / den);
+    for (int64_t i = 1; i < n; ++i) {
+        den = (lcplx)diag[i] - (lcplx)sub[i] * work[i - 1];
+        if (cabsl(den) == 0.0L) return -1;
+        work[i] = (lcplx)sup[i] / den;
+        x[i] = (cplx)(((lcplx)rhs[i] - (lcplx)sub[i] * (lcplx)x[i - 1]) / den);
+    }
+    for (int64_t i = n - 2; i >= 0; --i) x[i] = (cplx)((lcplx)x[i] - work[i] * (lcplx)x[i + 1]);
+    return 0;
+}
+
+/* One radial CN substep on every radial line (axis 0, contiguous). */
+static int radial_cn(int geom, const int64_t *n, const double *dx, double dt, int mode, cplx *psi)
+{
+    const int d = radial_dim(geom);
+    const int64_t nr = n[0], nlines = geom == ORACLE_AXIAL ? n[1] : 1;
+    const double dr = dx[0], tau = 0.5 * dt;
+    const cplx k = mode == ORACLE_REAL ? I * tau : tau;  /* implicit side W + k S, explicit W - k S */
+    cplx *sub = malloc(sizeof(cplx) * nr), *dia = malloc(sizeof(cplx) * nr), *sup = malloc(sizeof(cplx) * nr);
+    cplx *rhs = malloc(sizeof(cplx) * nr), *out = malloc(sizeof(cplx) * nr);
+    lcplx *work = malloc(sizeof(lcplx) * nr);
+    int status = 0;
+    for (int64_t line = 0; line < nlines && status == 0; ++line) {
+        cplx *u = psi + line * nr;
+        for (int64_t i = 0; i < nr; ++i) {
+            const double lo = radial_face(i, dr, d), hi = radial_face(i + 1, dr, d), w = radial_weight(i, dr, d);
+            const double s_d = (lo + hi) / (2.0 * dr * dr), s_lo = -lo / (2.0 * dr * dr), s_hi = -hi / (2.0 * dr * dr);
+            sub[i] = k * s_lo;
+            dia[i] = w + k * s_d;
+            sup[i] = k * s_hi;
+            cplx ex = (w - k * s_d) * u[i];
+            if (i > 0) ex -= k * s_lo * u[i - 1];
+            if (i + 1 < nr) ex -= k * s_hi * u[i + 1];
+            rhs[i] = ex;
+        }
+        status = thomas_general(nr, sub, dia, sup, rhs, out, work);
+        for (int64_t i = 0; i < nr; ++i) u[i] = out[i];
+    }
+    free(sub); free(dia); free(sup); free(rhs); free(out); free(work);
+    return status;
+}
+
+static double radial_norm(int geom, const int64_t *n, const double *dx, const cplx *psi)
+{
+    const int d = radial_dim(geom);
+    const int64_t nr = n[0], nz = geom == ORACLE_AXIAL ? n[1] : 1;
+    ksum s = {0.0, 0.0};
+    for (int64_t j = 0; j < nz; ++j)
+        for (int64_t i = 0; i < nr; ++i) ksum_add(&s, radial_weight(i, dx[0], d) * abs2(psi[j * nr + i]));
+    return radial_measure(geom, dx) * ksum_value(&s);
+}
+
+static double radial_potential(int geom, const int64_t *n, const double *dx, const double *omega, int64_t i, int64_t j)
+{
+    const double r = ((double)i + 0.5) * dx[0];
+    double v = 0.5 * omega[0] * omega[0] * r * r;
+    if (geom == ORACLE_AXIAL) {
+        const double z = coord(j, n[1], dx[1]);
+        v += 0.5 * omega[1] * omega[1] * z * z;
+    }
+    return v;
+}
+
+static int check_radial(int geom, const int64_t *n, const double *dx, double dt, int mode)
+{
+    if (geom != ORACLE_CIRCULAR && geom != ORACLE_SPHERICAL && geom != ORACLE_AXIAL) return -2;
+    const int nd = geom == ORACLE_AXIAL ? 2 : 1;
+    return check_args(nd, n, dx, dt, mode);
+}
+
+/* `nsteps` SSCN steps of a symmetric-trap problem: potential + nonlinear
+ * substep, CN along r (rho), then along z (axial), imaginary-time renormalisation.
+ * psi: (n[1], n[0]) for axial (rho fastest), (n[0]) otherwise. */
+int oracle_radial_step(int geom, const int64_t *n, const double *dx, double dt, int mode, const double *omega,
+                       double g, int64_t nsteps, double *psi_ri)
+{
+    int s = check_radial(geom, n, dx, dt, mode);
+    if (s) return s;
+    cplx *psi = (cplx *)psi_ri;
+    const int64_t nr = n[0], nz = geom == ORACLE_AXIAL ? n[1] : 1;
+    const int64_t zn[2] = {nr, nz};
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (int64_t j = 0; j < nz; ++j)
+            for (int64_t i = 0; i < nr; ++i) {
+                cplx *p = &psi[j * nr + i];
+                const double theta = dt * (radial_potential(geom, n, dx, omega, i, j) + g * abs2(*p));
+                if (mode == ORACLE_REAL)
+                    *p *= cexp(-I * theta);
+                else
+                    *p *= exp(-theta);
+            }
+        if (radial_cn(geom, n, dx, dt, mode, psi) != 0) return -1;
+        if (geom == ORACLE_AXIAL && cn_axis(2, zn, dx, dt, mode, 1, 0, psi) != 0) return -1;
+        if (mode == ORACLE_IMAG) {
+            const double nrm = radial_norm(geom, n, dx, psi);
+            if (!(nrm > 0.0) || !isfinite(nrm)) return -3;
+            const double scale = 1.0 / sqrt(nrm);
+            for (int64_t p = 0; p < nr * nz; ++p) psi[p] *= scale;
+        }
+    }
+    return 0;
+}
+
+/* out = {norm, mu, energy, ekin, epot, eint, rms_r (rho), rms_z, 0}. */
+int oracle_radial_observables(int geom, const int64_t *n, const double *dx, const double *omega, double g,
+                              const double *psi_ri, double *out)
+{
+    if (geom != ORACLE_CIRCULAR && geom != ORACLE_SPHERICAL && geom != ORACLE_AXIAL) return -2;
+    const cplx *psi = (const cplx *)psi_ri;
+    const int d = radial_dim(geom);
+    const int64_t nr = n[0], nz = geom == ORACLE_AXIAL ? n[1] : 1;
+    const double dr = dx[0], m = radial_measure(geom, dx);
+    ksum sn = {0, 0}, sv = {0, 0}, s4 = {0, 0}, sr2 = {0, 0}, sz2 = {0, 0}, kr = {0, 0}, kz = {0, 0};
+    for (int64_t j = 0; j < nz; ++j) {
+        for (int64_t i = 0; i < nr; ++i) {
+            const cplx u = psi[j * nr + i];
+            const double w = radial_weight(i, dr, d), dd = abs2(u), r = ((double)i + 0.5) * dr;
+            ksum_add(&sn, w * dd);
+            ksum_add(&sv, w * radial_potential(geom, n, dx, omega, i, j) * dd);
+            ksum_add(&s4, w * dd * dd);
+            ksum_add(&sr2, w * r * r * dd);
+            if (geom == ORACLE_AXIAL) {
+                const double z = coord(j, nz, dx[1]);
+                ksum_add(&sz2, w * z * z * dd);
+            }
+            /* radial faces i+1/2: to the next cell, or to the zero ghost past the last */
+            const cplx nxt = (i + 1 < nr) ? psi[j * nr + i + 1] : 0.0;
+            ksum_add(&kr, radial_face(i + 1, dr, d) * abs2(nxt - u));
+        }
+    }
+    if (geom == ORACLE_AXIAL)
+        for (int64_t i = 0; i < nr; ++i) {
+            const double w = radial_weight(i, dr, d);
+            for (int64_t j = -1; j < nz; ++j) {
+                const cplx lo = j >= 0 ? psi[j * nr + i] : 0.0, hi = j + 1 < nz ? psi[(j + 1) * nr + i] : 0.0;
+                ksum_add(&kz, w * abs2(hi - lo));
+            }
+        }
+    const double norm = m * ksum_value(&sn);
+    double ekin = 0.5 * m * ksum_value(&kr) / (dr * dr);
+    if (geom == ORACLE_AXIAL) ekin += 0.5 * m * ksum_value(&kz) / (dx[1] * dx[1]);
+    const double epot = m * ksum_value(&sv), eint = 0.5 * g * m * ksum_value(&s4);
+    out[0] = norm;
+    out[1] = ekin + epot + 2.0 * eint;
+    out[2] = ekin + epot + eint;
+    out[3] = ekin;
+    out[4] = epot;
+    out[5] = eint;
+    out[6] = sqrt(m * ksum_value(&sr2) / norm);
+    out[7] = geom == ORACLE_AXIAL ? sqrt(m * ksum_value(&sz2) / norm) : 0.0;
+    out[8] = 0.0;
+    return 0;
+}
+
