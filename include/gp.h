@@ -96,6 +96,11 @@ typedef struct {
 typedef struct gp_plan gp_plan;
 typedef struct gp_batch gp_batch;
 
+/* Trap symmetries ("Nature of problem": besides 1d and fully anisotropic 2d/3d
+ * traps, circularly symmetric 2d, spherically symmetric 3d and axially
+ * symmetric 3d traps, which reduce the dimension). */
+typedef enum { GP_CARTESIAN = 0, GP_CIRCULAR = 1, GP_SPHERICAL = 2, GP_AXIAL = 3 } gp_geometry;
+
 /* ------------------------------------------------------------ core path */
 
 /* Create a plan for an ndim-dimensional grid n[0..ndim) (x first) with
@@ -111,6 +116,22 @@ typedef struct gp_batch gp_batch;
  * enum, bad schedule), GP_ENOMEM, GP_EHIP (no usable device). */
 gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt,
                          gp_mode mode, const gp_trap *trap, double g, gp_prec prec);
+
+/* Create a plan for a symmetric trap ("Nature of problem"): GP_CIRCULAR
+ * (2d, psi(r)), GP_SPHERICAL (3d, psi(r)) -- n[0] radial points, dx[0] = dr,
+ * trap->omega[0] the radial frequency -- or GP_AXIAL (3d, psi(rho, z)) --
+ * n = {N_rho, N_z}, dx = {drho, dz}, omega = {w_rho, w_z}; the wavefunction is
+ * (N_z, N_rho) with rho fastest.  Radial points sit at r_i = (i + 1/2) dr, the
+ * wall is a zero ghost at i = N, and the radial Crank-Nicolson substep uses the
+ * finite-volume Laplacian with face areas r^(d-1) and exact cell volumes w_i as
+ * weights (self-adjoint in sum w conj(u) v, so real time conserves the norm);
+ * the axial z substep is the Cartesian one.  norm = m sum w |psi|^2 with
+ * m = 2 pi dr, 4 pi dr, 2 pi drho dz.  gp_step and gp_observables work on the
+ * plan (rms[0] = sqrt(<r^2>), rms[1] = sqrt(<z^2>) for axial); the adjoint and
+ * batched forms do not.  Errors: GP_EINVAL as gp_plan_create and for a bad
+ * geometry; GP_EUNSUPPORTED for GP_C64 or N_r (N_rho) above 1024. */
+gp_status gp_plan_create_sym(gp_plan **out, gp_geometry geom, const int64_t *n, const double *dx, double dt,
+                             gp_mode mode, const gp_trap *trap, double g, gp_prec prec);
 
 /* Free the plan and its device buffers (NULL is allowed). */
 gp_status gp_plan_destroy(gp_plan *plan);
@@ -285,7 +306,7 @@ gp_status gp_plan_timing_enable(gp_plan *plan, int64_t capacity);
 /* Synchronise the events and report, per kernel kind (names in
  * gp_kernel_name(kind), kind = 0..GP_NUM_KERNEL_KINDS-1), the number of
  * recorded launches and their total duration in milliseconds; clears the log. */
-#define GP_NUM_KERNEL_KINDS 14
+#define GP_NUM_KERNEL_KINDS 15
 gp_status gp_plan_timing_read(gp_plan *plan, int64_t *counts, double *total_ms);
 const char *gp_kernel_name(int kind);
 

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libgp.so")
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED, GP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GP_IMAG, GP_REAL = 0, 1
 GP_C128, GP_C64 = 0, 1
-GP_NUM_KERNEL_KINDS = 14
+GP_CARTESIAN, GP_CIRCULAR, GP_SPHERICAL, GP_AXIAL = 0, 1, 2, 3
+GP_NUM_KERNEL_KINDS = 15
 
 c_i64p = ctypes.POINTER(ctypes.c_int64)
 c_dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +67,7 @@ def lib():
         pp = ctypes.POINTER(ctypes.c_void_p)
         sig = {
             "gp_plan_create": [pp, i32, c_i64p, c_dp, d, i32, ctypes.POINTER(GpTrap), d, i32],
+            "gp_plan_create_sym": [pp, i32, c_i64p, c_dp, d, i32, ctypes.POINTER(GpTrap), d, i32],
             "gp_plan_destroy": [vp],
             "gp_step": [vp, vp, i64, vp],
             "gp_observables": [vp, vp, ctypes.POINTER(GpObs), vp],
@@ -144,10 +146,12 @@ def _check_psi(psi, shape, prec):
 
 class Plan:
     """Owns a gp_plan.  Grid sizes and spacings are given x first; tensors are
-    (Nz, Ny, Nx)-shaped, x fastest."""
+    (Nz, Ny, Nx)-shaped, x fastest.  geometry: GP_CARTESIAN (gp_plan_create) or a
+    symmetric trap (gp_plan_create_sym): GP_CIRCULAR / GP_SPHERICAL with n = (N_r,),
+    GP_AXIAL with n = (N_rho, N_z) and a (N_z, N_rho) tensor."""
 
     def __init__(self, n: Sequence[int], dx, dt: float, mode: int, omega=(0.0, 0.0, 0.0), g: float = 0.0,
-                 prec: int = GP_C128, sched=None, sched_axis: int = 0):
+                 prec: int = GP_C128, sched=None, sched_axis: int = 0, geometry: int = GP_CARTESIAN):
         L = lib()
         self.n = tuple(int(v) for v in n)
         self.ndim = len(self.n)
@@ -171,8 +175,13 @@ class Plan:
         n_arr = (ctypes.c_int64 * self.ndim)(*self.n)
         dx_arr = (ctypes.c_double * self.ndim)(*self.dx)
         h = ctypes.c_void_p()
-        check(L.gp_plan_create(ctypes.byref(h), self.ndim, n_arr, dx_arr, self.dt, self.mode,
-                               ctypes.byref(trap), self.g, self.prec), "gp_plan_create")
+        self.geometry = int(geometry)
+        if self.geometry == GP_CARTESIAN:
+            check(L.gp_plan_create(ctypes.byref(h), self.ndim, n_arr, dx_arr, self.dt, self.mode,
+                                   ctypes.byref(trap), self.g, self.prec), "gp_plan_create")
+        else:
+            check(L.gp_plan_create_sym(ctypes.byref(h), self.geometry, n_arr, dx_arr, self.dt, self.mode,
+                                       ctypes.byref(trap), self.g, self.prec), "gp_plan_create_sym")
         self._h = h
 
     @property

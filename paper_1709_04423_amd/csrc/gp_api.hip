@@ -290,10 +290,90 @@ static gp_status upload_table(gp_plan *p, AxisPlan &A, const std::vector<std::co
     return GP_OK;
 }
 
+// Radial axis of a symmetric-trap plan: the rows of the finite-volume CN system
+// (W + k S) psi' = (W - k S) psi on r_i = (i + 1/2) dr, k = i dt/2 (real time) or
+// dt/2 (imaginary time), with face areas a_{i+1/2} = ((i+1) dr)^(d-1), weights
+// w_i = r_i (d = 2) or r_i^2 + dr^2/12 (d = 3) and S = -1/2 W L:
+//   l_i = k s_{i,i-1}, diagonal w_i + k s_ii, u_i = k s_{i,i+1} (the wall coupling
+//   of the last row dropped: the ghost is zero);
+//   Thomas: m_i = 1/(diag_i - l_i c'_{i-1}), c'_i = u_i m_i;
+//   row p = (alpha_p = -m_p l_p, m_p, -c'_p, beta_p = w_p - k s_pp, l_p, u_p),
+// in long double, rounded once to double.  Rows past n are zero.  Also the scan
+// multipliers of the one-wavefront solver (Q points per lane): rows s = 0..5
+// forward, 6..11 backward, the lane's composite multiplier before scan step s.
+static void radial_tables(int64_t n, double dr, double dt, gp_mode mode, int d, int Q, std::vector<double> &rows,
+                          std::vector<double> &mul, double &rho)
+{
+    using cl = std::complex<long double>;
+    const int64_t nrows = (int64_t)Q * kLanes;
+    const long double tau = 0.5L * (long double)dt, h2 = (long double)dr * (long double)dr;
+    const cl k = mode == GP_REAL ? cl(0.0L, tau) : cl(tau, 0.0L);
+    std::vector<cl> fa(nrows, cl(0.0L, 0.0L)), ba(nrows, cl(0.0L, 0.0L));
+    rows.assign(12 * nrows, 0.0);
+    cl cprev(0.0L, 0.0L);
+    rho = 0.0;
+    auto face = [&](int64_t i) {
+        const long double r = (long double)i * (long double)dr;
+        return d == 3 ? r * r : r;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        const long double r = ((long double)i + 0.5L) * (long double)dr;
+        const long double w = d == 3 ? r * r + h2 / 12.0L : r;
+        const long double lo = face(i), hi = face(i + 1);
+        const long double sdd = (lo + hi) / (2.0L * h2), slo = -lo / (2.0L * h2), shi = -hi / (2.0L * h2);
+        const cl sub = k * slo, dia = cl(w, 0.0L) + k * sdd, sup = i + 1 < n ? k * shi : cl(0.0L, 0.0L);
+        const cl m = 1.0L / (dia - sub * cprev);
+        const cl c = sup * m;
+        const cl vals[6] = {-sub * m, m, -c, cl(w, 0.0L) - k * sdd, sub, sup};
+        for (int j = 0; j < 6; ++j) {
+            rows[12 * i + 2 * j] = (double)vals[j].real();
+            rows[12 * i + 2 * j + 1] = (double)vals[j].imag();
+        }
+        fa[i] = cl((long double)(double)vals[0].real(), (long double)(double)vals[0].imag());
+        ba[i] = cl((long double)(double)vals[2].real(), (long double)(double)vals[2].imag());
+        if (i + 1 < n) rho = std::fmax(rho, (double)std::abs(c));
+        cprev = c;
+    }
+    std::vector<cl> f(kLanes, cl(1.0L, 0.0L)), b(kLanes, cl(1.0L, 0.0L));
+    for (int L = 0; L < kLanes; ++L)
+        for (int i = 0; i < Q; ++i) {
+            f[L] *= fa[(int64_t)L * Q + i];
+            b[L] *= ba[(int64_t)L * Q + i];
+        }
+    mul.assign(2 * 12 * kLanes, 0.0);
+    for (int st = 0; st < 6; ++st) {
+        for (int L = 0; L < kLanes; ++L) {
+            mul[2 * (st * kLanes + L)] = (double)f[L].real();
+            mul[2 * (st * kLanes + L) + 1] = (double)f[L].imag();
+            mul[2 * ((6 + st) * kLanes + L)] = (double)b[L].real();
+            mul[2 * ((6 + st) * kLanes + L) + 1] = (double)b[L].imag();
+        }
+        const int dd = 1 << st;
+        std::vector<cl> f2 = f, b2 = b;
+        for (int L = 0; L < kLanes; ++L) {
+            if (L >= dd) f2[L] = f[L] * f[L - dd];
+            if (L + dd < kLanes) b2[L] = b[L] * b[L + dd];
+        }
+        f = f2;
+        b = b2;
+    }
+}
+
+static gp_status upload_doubles(gp_plan *p, const std::vector<double> &h, void **dst)
+{
+    gp_status st = alloc(dst, h.size() * sizeof(double), p->device_bytes);
+    if (st != GP_OK) return st;
+    hipError_t e = hipMemcpy(*dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(radial table)");
+    return GP_OK;
+}
+
 static void free_plan(gp_plan *p)
 {
     if (!p) return;
     for (int a = 0; a < 3; ++a) {
+        if (p->ax[a].d_rtab) hipFree(p->ax[a].d_rtab);
+        if (p->ax[a].d_rmul) hipFree(p->ax[a].d_rmul);
         if (p->ax[a].d_tab) hipFree(p->ax[a].d_tab);
         if (p->ax[a].d_tab_adj) hipFree(p->ax[a].d_tab_adj);
         if (p->ax[a].d_xmul) hipFree(p->ax[a].d_xmul);
@@ -364,13 +444,17 @@ const char *gp_kernel_name(int kind)
     static const char *names[GP_NUM_KERNEL_KINDS] = {
         "sweep_x", "sweep_y", "sweep_z", "sweep_exact", "scale", "observables",
         "observables_final", "adjoint_x", "adjoint_yz", "adjoint_reduce", "batch", "copy", "norm_final",
-        "sweep_xy"};
+        "sweep_xy", "radial_norm"};
     if (kind < 0 || kind >= GP_NUM_KERNEL_KINDS) return "unknown";
     return names[kind];
 }
 
-gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt, gp_mode mode,
-                         const gp_trap *trap, double g, gp_prec prec)
+}  // extern "C"
+
+// Plan of either kind: Cartesian (geom GP_CARTESIAN, ndim 1..3) or a symmetric
+// trap (radial axis 0; ndim 1, or 2 for axial).
+static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n, const double *dx, double dt,
+                             gp_mode mode, const gp_trap *trap, double g, gp_prec prec)
 {
     if (!out) return set_error("out is NULL"), GP_EINVAL;
     *out = nullptr;
@@ -401,8 +485,15 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
             if (!std::isfinite(trap->omega_sched[k])) return set_error("schedule value not finite"), GP_EINVAL;
     }
 
+    const bool radial = geom != GP_CARTESIAN;
+    if (radial && prec != GP_C128)
+        return set_error("symmetric-trap plans run in complex128 only"), GP_EUNSUPPORTED;
+    if (radial && n[0] > (int64_t)kLanes * kXMaxQ)
+        return set_error("symmetric-trap plans take at most 1024 radial points"), GP_EUNSUPPORTED;
+
     gp_plan *p = new (std::nothrow) gp_plan();
     if (!p) return set_error("host allocation failed"), GP_ENOMEM;
+    p->geom = geom;
     p->ndim = ndim;
     p->dt = dt;
     p->mode = mode;
@@ -415,11 +506,17 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         p->dx[a] = dx[a];
         p->dV *= dx[a];
     }
+    if (radial) {  // norm = m sum w |psi|^2
+        const double pi = 3.14159265358979323846;
+        p->dV = geom == GP_CIRCULAR ? 2.0 * pi * dx[0] : geom == GP_SPHERICAL ? 4.0 * pi * dx[0]
+                                                                              : 2.0 * pi * dx[0] * dx[1];
+    }
     if (trap) {
         for (int a = 0; a < ndim; ++a) p->omega[a] = trap->omega[a];
         if (trap->sched_len > 0) p->sched.assign(trap->omega_sched, trap->omega_sched + trap->sched_len);
         p->sched_axis = trap->sched_len > 0 ? trap->sched_axis : 0;
     }
+    std::vector<double> rrows, rmul;
 
     // host-side plan of each axis: line addressing, tables, window
     const int64_t nx = p->n[0], ny = p->n[1];
@@ -445,6 +542,15 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
             A.s2 = 0;
         }
         A.r = dt / (4.0 * dx[a] * dx[a]);
+        if (radial && a == 0) {  // variable-coefficient radial line: one wavefront per line, full scan
+            int Q = 1;
+            while ((int64_t)Q * kLanes < A.n) Q <<= 1;
+            A.rq = Q;
+            A.K = -1;
+            A.npad = (int64_t)Q * kLanes;
+            radial_tables(A.n, dx[0], dt, mode, radial_dim(geom), Q, rrows, rmul, A.rho);
+            continue;
+        }
         thomas_c(A.n, A.r, mode, cs[a], A.rho);
         // strided axes stream blocks of 4 rows per wavefront
         choose_window(A, prec, a == 0 ? kBlock : 4, a == 0);
@@ -463,7 +569,11 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
         return hip_fail(e, "hipGetDevice");
     }
     gp_status st = GP_OK;
-    for (int a = 0; a < ndim && st == GP_OK; ++a) {
+    if (radial) {
+        st = upload_doubles(p, rrows, &p->ax[0].d_rtab);
+        if (st == GP_OK) st = upload_doubles(p, rmul, &p->ax[0].d_rmul);
+    }
+    for (int a = radial ? 1 : 0; a < ndim && st == GP_OK; ++a) {
         st = upload_table(p, p->ax[a], cs[a], false, &p->ax[a].d_tab);
         if (st == GP_OK && mode == GP_REAL) st = upload_table(p, p->ax[a], cs[a], true, &p->ax[a].d_tab_adj);
         if (st == GP_OK && a == 0 && p->ax[0].xq > 0) {
@@ -476,9 +586,10 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     }
     int64_t maxg = 1;
     for (int a = 0; a < ndim; ++a) maxg = std::max(maxg, sweep_groups(p, a));
+    if (radial) maxg = std::max(maxg, radial_norm_groups(p));
     p->n_norm = maxg;
     p->n_adj = maxg;
-    p->n_obs_blocks = obs_groups(p);
+    p->n_obs_blocks = radial ? std::max<int64_t>(obs_groups(p), radial_norm_groups(p)) : obs_groups(p);
     if (st == GP_OK && ndim >= 2) st = alloc(&p->d_work, (size_t)npts * elem_bytes(prec), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_norm, (2 * maxg + 2) * sizeof(double), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_adj, 2 * maxg * sizeof(double), p->device_bytes);
@@ -491,9 +602,27 @@ gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double
     int max_lds = 0;
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
         max_lds = 0;
-    p->xy_segs = xy_choose_segments(p, max_lds);
+    p->xy_segs = radial ? 0 : xy_choose_segments(p, max_lds);
     *out = p;
     return GP_OK;
+}
+
+extern "C" {
+
+gp_status gp_plan_create(gp_plan **out, int ndim, const int64_t *n, const double *dx, double dt, gp_mode mode,
+                         const gp_trap *trap, double g, gp_prec prec)
+{
+    return create_plan(out, GP_CARTESIAN, ndim, n, dx, dt, mode, trap, g, prec);
+}
+
+gp_status gp_plan_create_sym(gp_plan **out, gp_geometry geom, const int64_t *n, const double *dx, double dt,
+                             gp_mode mode, const gp_trap *trap, double g, gp_prec prec)
+{
+    if (geom != GP_CIRCULAR && geom != GP_SPHERICAL && geom != GP_AXIAL) {
+        if (out) *out = nullptr;
+        return set_error("geometry must be GP_CIRCULAR, GP_SPHERICAL or GP_AXIAL"), GP_EINVAL;
+    }
+    return create_plan(out, geom, geom == GP_AXIAL ? 2 : 1, n, dx, dt, mode, trap, g, prec);
 }
 
 gp_status gp_plan_destroy(gp_plan *plan)
@@ -581,6 +710,27 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const bool imag = p->mode == GP_IMAG;
+    if (p->geom != GP_CARTESIAN) {  // symmetric trap: radial line solver, then z (axial)
+        for (int64_t k = 0; k < nsteps; ++k) {
+            const int64_t n = p->step + k;
+            const int fl = F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
+            if (p->ndim == 1) {
+                e = launch_radial_line(p, psi, psi, fl | (imag ? F_NORM_OUT : 0), n, s);
+            } else {
+                e = launch_radial_line(p, psi, p->d_work, fl, n, s);
+                if (e == hipSuccess) e = launch_sweep(p, 1, p->d_work, psi, 0, false, n, nullptr, s);
+                if (e == hipSuccess && imag) e = launch_radial_norm(p, psi, n, s);
+            }
+            if (e == hipSuccess && imag) e = launch_norm_final(p, n, s);
+            if (e != hipSuccess) return hip_fail(e, "symmetric-trap step launch");
+        }
+        p->step += nsteps;
+        if (imag) {
+            e = launch_scale(p, psi, s);
+            if (e != hipSuccess) return hip_fail(e, "scale launch");
+        }
+        return GP_OK;
+    }
     const bool fused = p->ndim == 3 && p->xy_segs > 0 && p->xy_enabled;
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n = p->step + k;
@@ -616,14 +766,35 @@ gp_status gp_observables(gp_plan *p, const void *psi, gp_obs *out, void *stream)
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    e = launch_observables(p, psi, s);
+    int64_t nb = p->n_obs_blocks;
+    if (p->geom != GP_CARTESIAN) {
+        nb = radial_norm_groups(p);
+        e = launch_radial_obs(p, psi, p->d_obs, nb, s);
+        if (e == hipSuccess) e = launch_obs_final(p, p->d_obs, nb, s);
+    } else {
+        e = launch_observables(p, psi, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "observables launch");
     double f[kObsFields];
-    e = hipMemcpyAsync(f, p->d_obs + p->n_obs_blocks * kObsFields, sizeof(f), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(f, p->d_obs + nb * kObsFields, sizeof(f), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(observables)");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    obs_from_sums(f, p->ndim, p->dx, p->g, out);
+    if (p->geom != GP_CARTESIAN) {  // weighted sums; m = the measure factor held in dV
+        const double m = p->dV;
+        out->norm = m * f[0];
+        out->epot = m * f[1];
+        out->eint = 0.5 * p->g * m * f[2];
+        out->ekin = 0.5 * m * f[6] / (p->dx[0] * p->dx[0]);
+        if (p->geom == GP_AXIAL) out->ekin += 0.5 * m * f[7] / (p->dx[1] * p->dx[1]);
+        out->energy = out->ekin + out->epot + out->eint;
+        out->mu = out->ekin + out->epot + 2.0 * out->eint;
+        out->rms[0] = std::sqrt(f[3] / f[0]);
+        out->rms[1] = p->geom == GP_AXIAL ? std::sqrt(f[4] / f[0]) : 0.0;
+        out->rms[2] = 0.0;
+    } else {
+        obs_from_sums(f, p->ndim, p->dx, p->g, out);
+    }
     if (!std::isfinite(out->norm) || !std::isfinite(out->energy)) {
         set_error("non-finite norm or energy");
         return GP_ENONFINITE;
@@ -635,6 +806,7 @@ gp_status gp_step_record(gp_plan *p, void *psi, int64_t nsteps, void *states, vo
 {
     if (!p || !psi || !states || nsteps < 0) return set_error("bad argument"), GP_EINVAL;
     if (p->mode != GP_REAL) return set_error("recording needs a real-time plan"), GP_EUNSUPPORTED;
+    if (p->geom != GP_CARTESIAN) return set_error("the adjoint form runs on Cartesian plans"), GP_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -653,6 +825,7 @@ gp_status gp_step_adjoint(gp_plan *p, const void *states, void *lambda, int64_t 
 {
     if (!p || !states || !lambda || nsteps < 0 || n_first < 0) return set_error("bad argument"), GP_EINVAL;
     if (p->mode != GP_REAL) return set_error("adjoint needs a real-time plan"), GP_EUNSUPPORTED;
+    if (p->geom != GP_CARTESIAN) return set_error("the adjoint form runs on Cartesian plans"), GP_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

@@ -27,6 +27,7 @@ enum KernelKind {
     K_COPY = 11,
     K_NORM_FINAL = 12,
     K_SWEEP_XY = 13,
+    K_RADIAL_NORM = 14,
 };
 
 // Flags of the line-sweep kernel.
@@ -76,6 +77,7 @@ struct SweepParams {
     double *norm_out;     // F_NORM_OUT partials, one per workgroup
     int64_t n_norm;       // partial slots per step parity (batched kernels offset by parity)
     double *adj_out;      // F_ADJ_N partials, two per workgroup
+    int radial_d;         // symmetric traps: dimension of the radial axis 0 (2 or 3; 0 Cartesian)
 };
 
 struct AxisPlan {
@@ -99,6 +101,10 @@ struct AxisPlan {
     void *d_tab_adj = nullptr;         // device table (conjugate)
     void *d_xmul = nullptr;            // x scan multipliers (forward map)
     void *d_xmul_adj = nullptr;        // x scan multipliers (conjugate map)
+    // radial axis of a symmetric-trap plan (axis 0): per-row coefficients and scan multipliers
+    void *d_rtab = nullptr;            // rows p = 0..64 rq - 1: alpha, m, -c', beta, l_p, l_{p+1} (complex)
+    void *d_rmul = nullptr;            // 12 x 64 complex: forward / backward lane multipliers per scan step
+    int rq = 0;                        // points per lane of the radial line solver
 };
 
 struct Timing {
@@ -111,6 +117,7 @@ struct Timing {
 }  // namespace gp
 
 struct gp_plan {
+    int geom = GP_CARTESIAN;        // gp_geometry: symmetric traps solve a radial axis 0
     int ndim = 1;
     int64_t n[3] = {1, 1, 1};
     double dx[3] = {1.0, 1.0, 1.0};
@@ -174,6 +181,7 @@ int xy_choose_segments(const gp_plan *p, int64_t max_lds);  // 0: the shape is n
 constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);
+hipError_t launch_obs_final(gp_plan *p, double *part, int64_t nb, hipStream_t s);  // row nb = sums of rows 0..nb-1
 // Observables from the kObsFields final sums (norm, E parts, mu, rms) of a grid.
 void obs_from_sums(const double *f, int ndim, const double *dx, double g, gp_obs *out);
 hipError_t launch_adj_reduce(gp_plan *p, int64_t nparts, double hw_coeff, double *dsched_k,
@@ -188,6 +196,15 @@ constexpr int kObsFields = 10;
 constexpr int kObsThreads = 256;
 
 void omega_at_step(const gp_plan *p, int64_t step, double w[3]);
+
+// Symmetric traps (gp_radial.hip).
+inline int radial_dim(int geom) { return geom == GP_SPHERICAL ? 3 : 2; }
+double axis_x0(const gp_plan *p, int axis);  // coordinate of index i on an axis: (i + x0) dx
+int64_t radial_line_groups(const gp_plan *p);
+int64_t radial_norm_groups(const gp_plan *p);
+hipError_t launch_radial_line(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
+hipError_t launch_radial_norm(gp_plan *p, const void *psi, int64_t step_index, hipStream_t s);
+hipError_t launch_radial_obs(gp_plan *p, const void *psi, double *part, int64_t nb, hipStream_t s);
 
 // Window choice of one axis exactly as gp_plan_create makes it (host only, no
 // device tables): for checks that must run before any HIP call.

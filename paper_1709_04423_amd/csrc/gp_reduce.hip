@@ -253,8 +253,9 @@ hipError_t launch_scale(gp_plan *p, void *psi, hipStream_t s)
 hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s)
 {
     timing_begin(p, K_NORM_FINAL, s);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, norm_partials(p, step_index),
-                       sweep_groups(p, p->ndim - 1), norm_total(p, step_index));
+    const int64_t np = p->geom == GP_AXIAL ? radial_norm_groups(p) : sweep_groups(p, p->ndim - 1);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, norm_partials(p, step_index), np,
+                       norm_total(p, step_index));
     timing_end(p, s);
     return hipGetLastError();
 }
@@ -290,6 +291,14 @@ static hipError_t launch_obs_kernels(int ndim, const int64_t *n, const double *d
     if (timed) timing_begin(timed, K_OBS_FINAL, s);
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, part, nb, part + nb * kObsFields);
     if (timed) timing_end(timed, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_final(gp_plan *p, double *part, int64_t nb, hipStream_t s)
+{
+    timing_begin(p, K_OBS_FINAL, s);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s, part, nb, part + nb * kObsFields);
+    timing_end(p, s);
     return hipGetLastError();
 }
 

@@ -5,8 +5,16 @@
 
 namespace gp {
 
+double axis_x0(const gp_plan *p, int axis)
+{
+    // radial axes are cell-centred from r = 0: r_i = (i + 1/2) dr
+    if (axis == 0 && p->geom != GP_CARTESIAN) return 0.5;
+    return coord0(p->n[axis]);
+}
+
 int64_t sweep_groups(const gp_plan *p, int axis)
 {
+    if (axis == 0 && p->geom != GP_CARTESIAN) return radial_line_groups(p);
     const AxisPlan &A = p->ax[axis];
     if (axis == 0 && A.xq > 0) return (A.nlines + kXWavesPerGroup * A.xlpw - 1) / (kXWavesPerGroup * A.xlpw);
     const int64_t g = (A.nlines + kLanes - 1) / kLanes;
@@ -44,7 +52,7 @@ SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void 
     omega_at_step(p, step_index, w);
     for (int a = 0; a < 3; ++a) {
         P.hw2[a] = a < p->ndim ? 0.5 * w[a] * w[a] : 0.0;
-        P.x0[a] = a < p->ndim ? coord0(p->n[a]) : 0.0;
+        P.x0[a] = a < p->ndim ? axis_x0(p, a) : 0.0;
         P.dx[a] = a < p->ndim ? p->dx[a] : 0.0;
     }
     P.ny = p->ndim >= 2 ? p->n[1] : 1;
@@ -65,6 +73,7 @@ SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void 
     P.xmul = adjoint ? A.d_xmul_adj : A.d_xmul;
     P.xq = A.xq;
     P.xlpw = A.xlpw;
+    P.radial_d = p->geom == GP_CARTESIAN ? 0 : radial_dim(p->geom);
     return P;
 }
 

@@ -220,7 +220,6 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int64_t n = P.n;
-    const int64_t q0 = (int64_t)lane * Q;
     auto pad = [](int q) { return q + q / Q; };  // slot of point q in xl
     const int S = P.scan_steps;
     const cp<R> zero = {R(0), R(0)};

@@ -152,6 +152,24 @@ def test_batch_create_rejects_problems_the_batched_kernels_do_not_run():
     assert binding.lib().gp_autotune(None, None) == binding.GP_EINVAL
 
 
+def test_symmetric_trap_plan_arguments_checked_before_hip():
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int64 * 2)(64, 32)
+    dx = (ctypes.c_double * 2)(0.1, 0.1)
+    # GP_CARTESIAN and out-of-range values are not symmetric geometries
+    for geom in (0, 4, -1):
+        assert L.gp_plan_create_sym(ctypes.byref(h), geom, n, dx, 1e-3, 0, None, 0.0, 0) == binding.GP_EINVAL
+    assert L.gp_plan_create_sym(ctypes.byref(h), binding.GP_AXIAL, n, dx, -1.0, 0, None, 0.0, 0) == binding.GP_EINVAL
+    # complex64 and radial lines beyond 1024 points are refused before any device work
+    assert L.gp_plan_create_sym(ctypes.byref(h), binding.GP_CIRCULAR, n, dx, 1e-3, 0, None, 0.0,
+                                1) == binding.GP_EUNSUPPORTED
+    big = (ctypes.c_int64 * 1)(1025)
+    assert L.gp_plan_create_sym(ctypes.byref(h), binding.GP_SPHERICAL, big, dx, 1e-3, 0, None, 0.0,
+                                0) == binding.GP_EUNSUPPORTED
+    assert not h.value
+
+
 def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))

@@ -1,0 +1,119 @@
+"""Symmetric traps on the GPU (gp_plan_create_sym through the C ABI) against
+the FP64 oracle's circular, spherical and axial programs: element by element
+and in every observable, within 1e-12 (complex128)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_04423_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_04423_amd import binding
+    binding.lib()
+    return binding
+
+
+GEOM = {"circular": oracle.CIRCULAR, "spherical": oracle.SPHERICAL, "axial": oracle.AXIAL}
+
+
+def start(geom, n, dx, seed):
+    if geom == oracle.AXIAL:
+        nr, nz = n
+        r = (np.arange(nr) + 0.5) * dx[0]
+        z = (np.arange(nz) - nz / 2) * dx[1]
+        psi = np.exp(-0.5 * r[None, :] ** 2 - z[:, None] ** 2)
+        return psi + 0.02 * inputs.random_field((nz, nr), seed)
+    r = (np.arange(n[0]) + 0.5) * dx[0]
+    return np.exp(-0.5 * r * r) + 0.02 * inputs.random_field((n[0],), seed)
+
+
+def run(gp, geom, n, dx, dt, mode, omega, g, steps, psi0):
+    plan = gp.Plan(n, dx, dt, mode, omega, g, gp.GP_C128, geometry=geom)
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to("cuda")
+    plan.step(psi, steps)
+    torch.cuda.synchronize()
+    odx = dx if geom == oracle.AXIAL else dx[0]
+    ref = oracle.radial_step(psi0, geom, odx, dt, mode, omega, g, steps)
+    return plan, psi, ref, odx
+
+
+def compare(gp, plan, psi, ref, geom, odx, omega, g, what):
+    got = psi.cpu().numpy()
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    o = plan.observables(psi)
+    r = oracle.radial_observables(ref, geom, odx, omega, g)
+    say(f"  {what}: psi err {err:.1e}, mu {o['mu']:.14f} (oracle {r['mu']:.14f})")
+    assert err <= TOL
+    for k, kk in (("norm", "norm"), ("mu", "mu"), ("energy", "energy"), ("ekin", "ekin"), ("epot", "epot"),
+                  ("eint", "eint"), ("rms_x", "rms_r"), ("rms_y", "rms_z")):
+        if r[kk] == 0.0:
+            assert o[k] == 0.0, k
+        else:
+            assert abs(o[k] - r[kk]) <= TOL * abs(r[kk]), (k, o[k], r[kk])
+
+
+CASES = [
+    ("circular", (1,), (0.1,)), ("circular", (37,), (0.15,)), ("circular", (512,), (0.02,)),
+    ("circular", (1024,), (0.01,)), ("spherical", (100,), (0.08,)), ("spherical", (700,), (0.015,)),
+    ("axial", (60, 64), (0.12, 0.1)), ("axial", (100, 37), (0.08, 0.2)), ("axial", (256, 200), (0.04, 0.05)),
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["imag", "real"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}")
+def test_symmetric_trap_steps_match_oracle(gp, case, mode):
+    name, n, dx = case
+    geom = GEOM[name]
+    omega = (1.0, 2.0) if geom == oracle.AXIAL else (1.0,)
+    psi0 = start(geom, n, dx, 50 + len(n))
+    plan, psi, ref, odx = run(gp, geom, n, dx, 2e-3, mode, omega, 40.0, 5, psi0)
+    compare(gp, plan, psi, ref, geom, odx, omega, 40.0, f"{name} {n} mode {mode}")
+
+
+@pytest.mark.parametrize("name", ["circular", "spherical", "axial"])
+def test_ground_state_then_quench_dynamics(gp, name):
+    # imaginary time to (near) the ground state, then a trap quench in real time,
+    # both phases against the oracle at full length
+    geom = GEOM[name]
+    if geom == oracle.AXIAL:
+        n, dx, om0, om1 = (128, 96), (0.08, 0.1), (1.0, 2.0), (0.8, 2.0)
+    else:
+        n, dx, om0, om1 = (400,), (0.025,), (1.0,), (1.25,)
+    g, dt = 100.0, 1e-3
+    psi0 = start(geom, n, dx, 7)
+    plan, psi, ref, odx = run(gp, geom, n, dx, dt, 0, om0, g, 1500, psi0)
+    compare(gp, plan, psi, ref, geom, odx, om0, g, f"{name} ground state")
+    real = gp.Plan(n, dx, dt, 1, om1, g, gp.GP_C128, geometry=geom)
+    real.step(psi, 1000)
+    ref = oracle.radial_step(ref, geom, odx, dt, 1, om1, g, 1000)
+    compare(gp, real, psi, ref, geom, odx, om1, g, f"{name} after 1000 real steps")
+
+
+def test_symmetric_trap_limits(gp):
+    with pytest.raises(gp.GpError) as e:
+        gp.Plan((64,), (0.1,), 1e-3, 0, (1.0,), 1.0, gp.GP_C64, geometry=gp.GP_CIRCULAR)
+    assert e.value.status == gp.GP_EUNSUPPORTED
+    with pytest.raises(gp.GpError) as e:
+        gp.Plan((1025,), (0.01,), 1e-3, 0, (1.0,), 1.0, gp.GP_C128, geometry=gp.GP_SPHERICAL)
+    assert e.value.status == gp.GP_EUNSUPPORTED
+    plan = gp.Plan((64,), (0.1,), 1e-3, 1, (1.0,), 1.0, gp.GP_C128, geometry=gp.GP_CIRCULAR)
+    psi = torch.zeros(64, dtype=torch.complex128, device="cuda")
+    states = torch.zeros((2, 64), dtype=torch.complex128, device="cuda")
+    with pytest.raises(gp.GpError) as e:
+        plan.step_record(psi, 1, states)
+    assert e.value.status == gp.GP_EUNSUPPORTED
