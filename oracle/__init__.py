@@ -267,3 +267,56 @@ def radial_observables(psi, geom, dx, omega, g) -> dict:
                                          g, _dp(a), _dp(out)), "radial_observables")
     return dict(zip(RADIAL_FIELDS, out[:8].tolist()))
 
+
+# ------------------------------------------------------------------ density outputs
+# "Summary of revisions": the programs write the condensate density, reduced
+# (integrated) 1d and 2d densities, and in real time the rms sizes as the
+# dynamics evolves after a perturbation.  Plain definitions, summed in a fixed
+# order (math.fsum, correctly rounded) over the integrated axes.
+
+def density(psi):
+    """|psi|^2 on the grid."""
+    a = np.asarray(psi, dtype=np.complex128)
+    return a.real * a.real + a.imag * a.imag
+
+
+def _fsum_axis(a, axis):
+    from math import fsum
+    moved = np.moveaxis(a, axis, -1)
+    out = np.empty(moved.shape[:-1])
+    for idx in np.ndindex(out.shape):
+        out[idx] = fsum(moved[idx])
+    return out
+
+
+def reduced_density(psi, dx, keep, weights=None):
+    """Integral of |psi|^2 over every axis not in `keep` (axes x = 0, y = 1, z = 2,
+    x first; psi shaped (Nz, Ny, Nx)).  weights: optional per-axis arrays that
+    multiply the integrand along that axis (the radial cell weights of a
+    symmetric trap); dx: spacing per axis (the measure of each integrated axis)."""
+    d = density(psi)
+    nd = d.ndim
+    dxs = list(np.broadcast_to(np.asarray(dx, dtype=np.float64), (nd,)))
+    keep = set(keep)
+    left = list(range(nd))  # grid axes still in d; numpy axis of grid axis a = len(left) - 1 - left.index(a)
+    for a in sorted(set(range(nd)) - keep, reverse=True):  # integrate the slowest axes first
+        ax = len(left) - 1 - left.index(a)
+        if weights is not None and weights.get(a) is not None:
+            shape = [1] * d.ndim
+            shape[ax] = -1
+            d = d * np.asarray(weights[a]).reshape(shape)
+        d = _fsum_axis(d, ax) * dxs[a]
+        left.remove(a)
+    return d
+
+
+def series(psi, dx, dt, mode, omega, g, nsteps, every):
+    """Observables at steps 0, every, 2 every, ..., nsteps of an SSCN run
+    (the rms-dynamics output of the real-time programs)."""
+    out = [observables(psi, dx, omega, g)]
+    p = psi
+    for _ in range(nsteps // every):
+        p = step(p, dx, dt, mode, omega, g, every)
+        out.append(observables(p, dx, omega, g))
+    return out
+

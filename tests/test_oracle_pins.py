@@ -478,3 +478,40 @@ def test_threads_do_not_change_results():
         env = dict(os.environ, OMP_NUM_THREADS=t, PYTHONPATH=root)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env, cwd=root).decode())
     assert outs[0] == outs[1]
+
+
+# ------------------------------------------------------- density outputs
+
+def test_reduced_densities_of_a_product_state_are_its_marginals():
+    # a product of 1D Gaussians: integrating out axes leaves the product of the
+    # remaining 1D factors times the Riemann sums of the integrated ones
+    n, dx, om = (40, 30, 20), (0.2, 0.25, 0.3), (1.0, 2.0, 3.0)
+    psi = inputs.gaussian(n, dx, om)
+    f = [np.abs(inputs.gaussian((n[a],), dx[a], (om[a],))) ** 2 for a in range(3)]
+    m = [dx[a] * np.sum(f[a]) for a in range(3)]  # Riemann sum of each factor
+    for keep in range(3):
+        got = oracle.reduced_density(psi, dx, [keep])
+        others = [a for a in range(3) if a != keep]
+        assert np.allclose(got, f[keep] * m[others[0]] * m[others[1]], rtol=1e-14, atol=0)
+    got = oracle.reduced_density(psi, dx, [0, 2])  # integrate y out: (Nz, Nx)
+    assert np.allclose(got, np.outer(f[2], f[0]) * m[1], rtol=1e-14, atol=0)
+    assert abs(dx[0] * np.sum(oracle.reduced_density(psi, dx, [0])) - oracle.observables(psi, dx, om, 0)["norm"]) < 1e-14
+
+
+def test_reduced_density_integrates_to_the_norm_on_a_random_field():
+    psi = inputs.random_field((9, 11, 13), 21)
+    dx = (0.1, 0.2, 0.3)
+    norm = oracle.observables(psi, dx, (0, 0, 0), 0.0)["norm"]
+    for keep in ([0], [1], [2], [0, 1], [1, 2], [0, 2]):
+        d = oracle.reduced_density(psi, dx, keep)
+        cell = np.prod([dx[a] for a in keep])
+        assert abs(cell * np.sum(d) - norm) <= 1e-13 * norm, keep
+
+
+def test_series_records_the_observables_of_each_step_block():
+    n, dx, om, g, dt = (24, 20), (0.2, 0.25), (1.0, 1.3), 20.0, 1e-3
+    psi = inputs.gaussian(n, dx, om) + 0.01 * inputs.random_field((20, 24), 22)
+    rec = oracle.series(psi, dx, dt, oracle.REAL, om, g, 30, 10)
+    assert len(rec) == 4
+    assert rec[0] == oracle.observables(psi, dx, om, g)
+    assert rec[3] == oracle.observables(oracle.step(psi, dx, dt, oracle.REAL, om, g, 30), dx, om, g)
