@@ -276,6 +276,38 @@ gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ys
  * NULL batch or k outside 0..count-1. */
 gp_status gp_batch_observables(gp_batch *batch, int k, const void *psi, gp_obs *out, void *stream);
 
+/* -------------------------------------------------------- density outputs */
+/* "Summary of revisions" lists the programs' density outputs: the condensate
+ * density, reduced (integrated) 1d and 2d densities, and in the real-time
+ * programs the rms sizes as the dynamics evolves after a perturbation.  These
+ * compute them on the device beside the step; out buffers are caller-owned
+ * device FP64 arrays; every call is asynchronous on `stream`. */
+
+/* out[p] = |psi_p|^2 at every grid point p (plan layout, npts values).
+ * GP_EINVAL for NULL arguments. */
+gp_status gp_density(gp_plan *plan, const void *psi, double *out, void *stream);
+
+/* |psi|^2 integrated over every axis whose bit is clear in keep_mask (bit a =
+ * axis a, x = bit 0), by rectangle sums in a fixed order; out holds the kept
+ * axes' grid, x fastest -- e.g. keep_mask 4 on a 3D plan gives
+ * n(z_k) = sum_{i,j} |psi_ijk|^2 dx dy (npts / (nx ny) values).  Cartesian plans
+ * of 2 or 3 dimensions and axial plans; for an axial plan integrating rho
+ * carries the weights 2 pi r_i drho (keep z: the linear density n(z), summing
+ * to the norm with dz) and integrating z gives the column density of each rho.
+ * A two-axis integration leaves its intermediate in the plan's work grid.
+ * GP_EINVAL for NULL arguments, a mask that keeps no axis or all of them, or a
+ * 1D (including circular / spherical) plan. */
+gp_status gp_density_reduced(gp_plan *plan, const void *psi, int keep_mask, double *out, void *stream);
+
+/* Advance psi by nsteps steps exactly as gp_step, in blocks of `every` steps,
+ * recording the observables of the state before the first block and after
+ * every block: out (device) receives nsteps/every + 1 records of
+ * GP_SERIES_FIELDS FP64 values -- step index, norm, mu, energy, ekin, epot,
+ * eint, rms[0], rms[1], rms[2] (as gp_obs) -- with no host synchronisation.
+ * GP_EINVAL unless nsteps is a non-negative multiple of every >= 1. */
+#define GP_SERIES_FIELDS 10
+gp_status gp_step_series(gp_plan *plan, void *psi, int64_t nsteps, int64_t every, double *out, void *stream);
+
 /* --------------------------------------- observables without allocation */
 
 /* For callers that cannot allocate device memory -- code under HIP graph

@@ -91,6 +91,9 @@ def lib():
             "gp_plan_timing_read": [vp, c_i64p, c_dp],
             "gp_copy_probe": [vp, vp, i64, vp],
             "gp_observables_noalloc": [i32, c_i64p, c_dp, c_dp, d, i32, vp, ctypes.POINTER(GpObs), vp],
+            "gp_density": [vp, vp, vp, vp],
+            "gp_density_reduced": [vp, vp, i32, vp, vp],
+            "gp_step_series": [vp, vp, i64, i64, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -142,6 +145,13 @@ def _check_psi(psi, shape, prec):
         raise ValueError("psi must be contiguous")
     if _prec_of(psi.dtype) != prec:
         raise TypeError("psi dtype does not match the plan precision")
+
+
+def _check_f64(t, shape):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() \
+            or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
 
 
 class Plan:
@@ -225,6 +235,43 @@ class Plan:
         check(lib().gp_step_record(self._h, ctypes.c_void_p(psi.data_ptr()), int(nsteps),
                                    ctypes.c_void_p(states.data_ptr()), _stream_handle(stream)), "gp_step_record")
         return psi
+
+    def density(self, psi, out=None, stream=None):
+        """|psi|^2 on the grid (float64 device tensor of psi's shape)."""
+        import torch
+        _check_psi(psi, self.shape, self.prec)
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=psi.device)
+        _check_f64(out, tuple(self.shape))
+        check(lib().gp_density(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               _stream_handle(stream)), "gp_density")
+        return out
+
+    def density_reduced(self, psi, keep, stream=None):
+        """|psi|^2 integrated over the axes not in `keep` (axis numbers, x = 0): a float64
+        tensor over the kept axes (slowest first, as the grid)."""
+        import torch
+        _check_psi(psi, self.shape, self.prec)
+        mask = 0
+        for a in keep:
+            mask |= 1 << int(a)
+        kept = tuple(self.n[a] for a in sorted(keep))[::-1]
+        out = torch.empty(kept, dtype=torch.float64, device=psi.device)
+        check(lib().gp_density_reduced(self._h, ctypes.c_void_p(psi.data_ptr()), mask,
+                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "gp_density_reduced")
+        return out
+
+    def step_series(self, psi, nsteps: int, every: int, stream=None):
+        """Steps as step() with the observables every `every` steps: a float64 device tensor of
+        shape (nsteps/every + 1, 10): step, norm, mu, energy, ekin, epot, eint, rms[3]."""
+        import torch
+        _check_psi(psi, self.shape, self.prec)
+        if every < 1 or nsteps < 0 or nsteps % every:
+            raise ValueError("nsteps must be a non-negative multiple of every >= 1")
+        out = torch.empty((nsteps // every + 1, 10), dtype=torch.float64, device=psi.device)
+        check(lib().gp_step_series(self._h, ctypes.c_void_p(psi.data_ptr()), int(nsteps), int(every),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "gp_step_series")
+        return out
 
     def set_step(self, step: int):
         check(lib().gp_plan_set_step(self._h, int(step)), "gp_plan_set_step")
