@@ -189,6 +189,23 @@ gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable);
 gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec prec, int adjoint,
                           double *c, double *beta, int *window, double *rho);
 
+/* --------------------------------------------------- physical inputs (host) */
+/* "Summary of revisions": the programs take physical inputs (number of atoms,
+ * scattering length, oscillator length, trap anisotropy) and compute the
+ * dimensionless nonlinearity from them.  In units of the oscillator length
+ * l = sqrt(hbar / (m w)) and of hbar w, the 3d equation has g = 4 pi N a / l.
+ * A tight confinement integrates out: in 2d (z frequency lambda w) g is
+ * multiplied by the integral of the z ground state's |zeta|^4,
+ * sqrt(lambda / (2 pi)); in 1d (transverse frequency nu w) by the transverse
+ * ground state's, nu / (2 pi).  a in Bohr radii (5.29177210903e-11 m), l in
+ * micrometres, confine = lambda (ndim 2) or nu (ndim 1), ignored in 3d.
+ * GP_EINVAL for non-finite or out-of-range inputs or a NULL output. */
+gp_status gp_nonlinearity(int ndim, double natoms, double a_bohr, double l_micron, double confine, double *g);
+
+/* Oscillator length sqrt(hbar / (m 2 pi f)) in micrometres for an atomic mass
+ * in atomic mass units and a trap frequency f in Hz (CODATA hbar and u). */
+gp_status gp_osc_length(double mass_amu, double freq_hz, double *l_micron);
+
 const char *gp_strerror(gp_status s);
 const char *gp_last_error(void);
 

@@ -92,6 +92,8 @@ def lib():
             "gp_copy_probe": [vp, vp, i64, vp],
             "gp_observables_noalloc": [i32, c_i64p, c_dp, c_dp, d, i32, vp, ctypes.POINTER(GpObs), vp],
             "gp_density": [vp, vp, vp, vp],
+            "gp_nonlinearity": [i32, d, d, d, d, c_dp],
+            "gp_osc_length": [d, d, c_dp],
             "gp_density_reduced": [vp, vp, i32, vp, vp],
             "gp_step_series": [vp, vp, i64, i64, vp, vp],
         }
@@ -400,6 +402,22 @@ def thomas_table(n: int, dx: float, dt: float, mode: int, prec: int = GP_C128, a
                                 c.ctypes.data_as(c_dp), beta.ctypes.data_as(c_dp), ctypes.byref(K),
                                 ctypes.byref(rho)), "gp_thomas_table")
     return c.view(np.complex128), beta.view(np.complex128), K.value, rho.value
+
+
+def nonlinearity(ndim: int, natoms: float, a_bohr: float, l_micron: float, confine: float = 1.0) -> float:
+    """gp_nonlinearity: dimensionless g from N, a (Bohr radii), l (micrometres) and the
+    confinement ratio lambda (2D) or nu (1D)."""
+    g = ctypes.c_double()
+    check(lib().gp_nonlinearity(int(ndim), float(natoms), float(a_bohr), float(l_micron), float(confine),
+                                ctypes.byref(g)), "gp_nonlinearity")
+    return g.value
+
+
+def osc_length(mass_amu: float, freq_hz: float) -> float:
+    """gp_osc_length: sqrt(hbar / (m 2 pi f)) in micrometres."""
+    v = ctypes.c_double()
+    check(lib().gp_osc_length(float(mass_amu), float(freq_hz), ctypes.byref(v)), "gp_osc_length")
+    return v.value
 
 
 def observables_noalloc(psi, dx, omega=None, g: float = 0.0, stream=None) -> dict:

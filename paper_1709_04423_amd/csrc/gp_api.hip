@@ -664,6 +664,31 @@ gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable)
     return GP_OK;
 }
 
+gp_status gp_osc_length(double mass_amu, double freq_hz, double *l_micron)
+{
+    if (!l_micron || !(mass_amu > 0.0) || !(freq_hz > 0.0) || !std::isfinite(mass_amu) || !std::isfinite(freq_hz))
+        return set_error("mass and frequency must be finite and > 0"), GP_EINVAL;
+    const double hbar = 1.054571817e-34, amu = 1.66053906660e-27, pi = 3.14159265358979323846;
+    *l_micron = std::sqrt(hbar / (mass_amu * amu * 2.0 * pi * freq_hz)) * 1e6;
+    return GP_OK;
+}
+
+gp_status gp_nonlinearity(int ndim, double natoms, double a_bohr, double l_micron, double confine, double *g)
+{
+    if (!g || ndim < 1 || ndim > 3 || !std::isfinite(natoms) || natoms < 0.0 || !std::isfinite(a_bohr) ||
+        !(l_micron > 0.0) || !std::isfinite(l_micron) || (ndim < 3 && (!(confine > 0.0) || !std::isfinite(confine))))
+        return set_error("bad physical input"), GP_EINVAL;
+    const double bohr = 5.29177210903e-11, pi = 3.14159265358979323846;
+    const double na_l = natoms * a_bohr * bohr / (l_micron * 1e-6);  // N a / l
+    if (ndim == 3)
+        *g = 4.0 * pi * na_l;
+    else if (ndim == 2)  // integral of the z ground state's |zeta|^4 = sqrt(lambda / (2 pi))
+        *g = 4.0 * pi * na_l * std::sqrt(confine / (2.0 * pi));
+    else  // integral of the transverse (2D) ground state's |zeta|^4 = nu / (2 pi)
+        *g = 4.0 * pi * na_l * confine / (2.0 * pi);
+    return GP_OK;
+}
+
 gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec prec, int adjoint, double *c,
                           double *beta, int *window, double *rho)
 {
