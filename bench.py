@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--traffic-kernel", default="k_sweep_xy<double",
                     help="kernel-name prefix whose bytes per launch the traffic summary records")
     ap.add_argument("--step-kernels", default="",
-                    help="comma-separated kernel-name prefixes launched once per step: the traffic summary "
+                    help="semicolon-separated kernel-name prefixes (optionally @grid-size) launched once per step: the traffic summary "
                          "also records their summed bytes per launch as bytes_per_step")
     return ap.parse_args()
 
@@ -470,49 +470,58 @@ def summarize_trace(directory, out, title, command):
 
 
 def _counter_means(directory, counter):
+    """Mean counter value per dispatch, keyed by (kernel name, grid size): the same
+    kernel launched on different grids (workloads) is kept apart."""
     per = {}
     for r in _csv_rows(directory, "counter_collection.csv"):
         if r.get("Counter_Name") != counter:
             continue
-        name = r["Kernel_Name"]
-        per.setdefault(name, {}).setdefault(r["Dispatch_Id"], 0.0)
-        per[name][r["Dispatch_Id"]] += float(r["Counter_Value"])  # summed over dimensions of one dispatch
+        key = (r["Kernel_Name"], int(r["Grid_Size"]))
+        per.setdefault(key, {}).setdefault(r["Dispatch_Id"], 0.0)
+        per[key][r["Dispatch_Id"]] += float(r["Counter_Value"])  # summed over dimensions of one dispatch
     return {k: (len(v), sum(v.values()) / len(v)) for k, v in per.items()}
+
+
+def _selects(key, selector):
+    """selector 'name-prefix' or 'name-prefix@grid-size'."""
+    prefix, _, grid = selector.partition("@")
+    return _short(key[0]).startswith(prefix) and (not grid or key[1] == int(grid))
 
 
 def summarize_traffic(fetch_dir, write_dir, out, title, command, kernel_prefix, step_kernels=""):
     fetch = _counter_means(fetch_dir, "FETCH_SIZE")
     write = _counter_means(write_dir, "WRITE_SIZE")
-    copy = [k for k in fetch if _short(k).startswith("k_copy")]
+    copy = [k for k in fetch if _short(k[0]).startswith("k_copy")]
     if not copy:
         raise SystemExit("the profiled run must include the 1 GiB copy probe (k_copy) for calibration")
     kib = float(1 << 20)  # 1 GiB copied = 2^20 KiB each way
     fscale = kib / fetch[copy[0]][1]
-    wscale = kib / write[[k for k in write if _short(k).startswith("k_copy")][0]][1]
+    wscale = kib / write[[k for k in write if _short(k[0]).startswith("k_copy")][0]][1]
     lines = [f"# HBM traffic per launch: {title}", "", "Commands (one counter per run; REPO = repository root, "
              "OUT = any output directory):", ""] + [f"    {c}" for c in command.split(" ;; ")] + [
         "", f"Calibration: the copy kernel `k_copy` moves exactly 1 GiB each way per launch; its counters read "
             f"FETCH_SIZE = {fetch[copy[0]][1]:.1f} KiB and WRITE_SIZE = {kib / wscale:.1f} KiB, so read bytes = "
             f"FETCH_SIZE x {fscale:.4f} KiB and write bytes = WRITE_SIZE x {wscale:.4f} KiB.", "",
-        "| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |", "|---|---|---|---|---|---|"]
+        "| kernel | grid size | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |",
+        "|---|---|---|---|---|---|---|"]
     chosen = None
-    step_prefixes = [p for p in step_kernels.split(",") if p]
+    step_prefixes = [p for p in step_kernels.split(";") if p]
     step_bytes = {}
-    for name in sorted(fetch, key=lambda k: -fetch[k][1]):
-        n, f = fetch[name]
-        wv = write.get(name, (0, 0.0))[1]
+    for key in sorted(fetch, key=lambda k: -fetch[k][1]):
+        n, f = fetch[key]
+        wv = write.get(key, (0, 0.0))[1]
         rb, wb = f * fscale * 1024, wv * wscale * 1024
-        lines.append(f"| `{_short(name)}` | {n} | {f:.1f} | {wv:.1f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
-        if chosen is None and _short(name).startswith(kernel_prefix):
-            chosen = (name, rb, wb)
+        lines.append(f"| `{_short(key[0])}` | {key[1]} | {n} | {f:.1f} | {wv:.1f} | {rb / 1e6:.1f} | {wb / 1e6:.1f} |")
+        if chosen is None and _selects(key, kernel_prefix):
+            chosen = (f"{_short(key[0])} (grid {key[1]})", rb, wb)
         for p in step_prefixes:
-            if _short(name).startswith(p):
+            if _selects(key, p):
                 # instantiations of one kernel kind: launch-weighted mean
                 c, tot = step_bytes.get(p, (0, 0.0))
                 step_bytes[p] = (c + n, tot + n * (rb + wb))
     lines += ["", "Recorded for the benchmark (dominant kernel, read by bench.py while the source hash matches):", ""]
     if chosen:
-        lines += [f"- kernel: `{_short(chosen[0])}`", f"- kernel_source_hash: {kernel_source_hash()}",
+        lines += [f"- kernel: `{chosen[0]}`", f"- kernel_source_hash: {kernel_source_hash()}",
                   f"- read_bytes: {int(chosen[1])}", f"- write_bytes: {int(chosen[2])}",
                   f"- bytes_per_launch: {int(chosen[1] + chosen[2])}"]
     if step_prefixes and len(step_bytes) == len(step_prefixes):
