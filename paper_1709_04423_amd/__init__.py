@@ -5,4 +5,4 @@ The numerics run in hand-written HIP kernels for gfx950 behind a C-ABI library
 over it.  Submodules are imported on demand so that input generation works on a
 machine without a GPU.
 """
-__all__ = ["binding", "inputs", "solver", "adjoint"]
+__all__ = ["binding", "inputs", "adjoint", "workflow"]
