@@ -66,13 +66,44 @@ template <int MODE, typename R> __device__ __forceinline__ cp<R> kfma(cp<R> k, c
     if (MODE == GP_IMAG) return {fma(k.re, v.re, w.re), fma(k.re, v.im, w.im)};
     return cfma(k, v, w);
 }
+// Whole-wavefront shifts by one lane as DPP moves (wave_shr:1 / wave_shl:1): a
+// VALU operation instead of an LDS permute round trip, on the scan's critical
+// chain.  The lane shifted in from outside the wavefront receives 0 (callers
+// discard or zero those lanes anyway).
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+
+template <bool UP> __device__ __forceinline__ double dpp_shift1(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int slo = UP ? dpp_shr1(lo) : dpp_shl1(lo), shi = UP ? dpp_shr1(hi) : dpp_shl1(hi);
+    return __longlong_as_double(((long long)shi << 32) | (long long)(unsigned)slo);
+}
+template <bool UP> __device__ __forceinline__ float dpp_shift1(float v)
+{
+    const int b = __float_as_int(v);
+    return __int_as_float(UP ? dpp_shr1(b) : dpp_shl1(b));
+}
+
+// Lane L receives lane L - d (UP) or L + d: shifts of 1, 2 and 4 lanes are that
+// many DPP moves, longer ones a permute.  d is a compile-time constant wherever
+// these are used in unrolled loops, so the branch folds away.
+template <bool UP, typename R> __device__ __forceinline__ R lane_shift(R v, int d)
+{
+    if (d == 1 || d == 2 || d == 4) {
+        for (int k = 0; k < d; ++k) v = dpp_shift1<UP>(v);
+        return v;
+    }
+    return UP ? __shfl_up(v, d, kLanes) : __shfl_down(v, d, kLanes);
+}
 template <typename R> __device__ __forceinline__ cp<R> shfl_up_c(cp<R> v, int d)
 {
-    return {__shfl_up(v.re, d, kLanes), __shfl_up(v.im, d, kLanes)};
+    return {lane_shift<true>(v.re, d), lane_shift<true>(v.im, d)};
 }
 template <typename R> __device__ __forceinline__ cp<R> shfl_down_c(cp<R> v, int d)
 {
-    return {__shfl_down(v.re, d, kLanes), __shfl_down(v.im, d, kLanes)};
+    return {lane_shift<false>(v.re, d), lane_shift<false>(v.im, d)};
 }
 
 // Table row of point q: (c', beta, beta_lo); constant past q_const, zero past n.
