@@ -170,8 +170,10 @@ gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info);
  * method") act plane by plane, so where the plan's shape allows (x extent 128,
  * 192 or 256, and a y window of 2..4 blocks that fits in LDS) one kernel reads
  * each xy-plane once and writes the result of both substeps; otherwise, or
- * when disabled, the sweeps run as separate kernels.  Both give the same step
- * up to rounding.  GP_EINVAL for a NULL plan or a flag other than 0 or 1. */
+ * when disabled, the sweeps run as separate kernels.  enable = 2 (the default)
+ * keeps the y solver's elimination window in registers and double-buffers the
+ * row tile; enable = 1 keeps the window in LDS.  Every choice gives the same
+ * step up to rounding.  GP_EINVAL for a NULL plan or a flag outside 0..2. */
 gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable);
 
 /* Host-only (no GPU needed): one axis's Thomas table exactly as a plan stores

@@ -285,9 +285,10 @@ class Plan:
                 "window_bound": tuple(i.window_bound), "step": i.step, "device_bytes": i.device_bytes,
                 "xy_fused": i.xy_fused}
 
-    def set_xy_fusion(self, enable: bool):
-        """3D: use (True, the default) or skip the fused x+y sweep where the shape allows it."""
-        check(lib().gp_plan_set_xy_fusion(self._h, int(bool(enable))), "gp_plan_set_xy_fusion")
+    def set_xy_fusion(self, enable):
+        """3D: skip (0/False) the fused x+y sweep, or use it where the shape allows:
+        2 (the default) with the y window in registers, 1 (True) with it in LDS."""
+        check(lib().gp_plan_set_xy_fusion(self._h, int(enable)), "gp_plan_set_xy_fusion")
 
     def adjoint(self, states, lam, n_first: int, nsteps: int, dsched=None, dg=None, stream=None):
         """Reverse nsteps real-time steps (see gp_step_adjoint)."""

@@ -602,7 +602,8 @@ static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n
     int max_lds = 0;
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess)
         max_lds = 0;
-    p->xy_segs = radial ? 0 : xy_choose_segments(p, max_lds);
+    p->max_lds = max_lds;
+    p->xy_segs = radial ? 0 : xy_choose_segments(p, p->xy_variant, max_lds);
     *out = p;
     return GP_OK;
 }
@@ -659,8 +660,14 @@ gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info)
 
 gp_status gp_plan_set_xy_fusion(gp_plan *plan, int enable)
 {
-    if (!plan || (enable != 0 && enable != 1)) return set_error("bad plan or flag"), GP_EINVAL;
+    if (!plan || enable < 0 || enable > 2) return set_error("bad plan or flag"), GP_EINVAL;
     plan->xy_enabled = enable != 0;
+    if (enable && enable != plan->xy_variant && plan->geom == GP_CARTESIAN) {
+        const hipError_t e = hipSetDevice(plan->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        plan->xy_variant = enable;
+        plan->xy_segs = xy_choose_segments(plan, enable, plan->max_lds);
+    }
     return GP_OK;
 }
 

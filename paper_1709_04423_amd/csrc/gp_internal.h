@@ -143,6 +143,8 @@ struct gp_plan {
     int64_t device_bytes = 0;
     int xy_segs = 0;                // 3D: row segments per plane of the fused x+y kernel (0: not fusable)
     bool xy_enabled = true;         // use the fused kernel when xy_segs > 0
+    int xy_variant = 2;             // fused kernel: 1 LDS elimination window, 2 window in registers
+    int max_lds = 0;                // LDS bytes a workgroup may use on the plan's device
     gp::Timing timing;
 };
 
@@ -176,8 +178,10 @@ inline double *norm_total(gp_plan *p, int64_t step) { return p->d_norm + 2 * p->
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
 // Fused x and y sweeps of a 3D step (src -> dst, x flags as for the x sweep).
 hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
-size_t xy_lds_bytes(const gp_plan *p);
-int xy_choose_segments(const gp_plan *p, int64_t max_lds);  // 0: the shape is not fusable
+size_t xy_lds_bytes(const gp_plan *p, int variant);
+// Row segments per plane of the fused kernel variant on this plan's device (0:
+// the shape is not fusable).
+int xy_choose_segments(const gp_plan *p, int variant, int64_t max_lds);
 constexpr int kXWavesPerGroup = 4;  // wavefronts per workgroup of the x scan kernel
 constexpr int kXMaxQ = 16;          // largest points per lane of the x scan kernel
 hipError_t launch_observables(gp_plan *p, const void *psi, hipStream_t s);

@@ -14,6 +14,7 @@
 // zero state, like the strided sweeps' segments; the x rows of those warm-up
 // blocks are solved again by the segment that needs them.
 #include <algorithm>
+#include <utility>
 
 #include "gp_internal.h"
 #include "gp_sweep_common.h"
@@ -134,58 +135,235 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
     }
 }
 
-template <typename R, int MODE, int XFLAGS, int Q, int DW>
-static void launch_xy_dw(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s)
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N-1>), in order: a loop
+// whose index is a compile-time constant in every copy.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
 {
-    using V = typename CT<R>::V;
-    const size_t ring = (size_t)kXYWaves * (PY.lmask + 1) * kLanes * sizeof(V);
-    hipLaunchKernelGGL((k_sweep_xy<R, MODE, XFLAGS, Q, DW>), dim3((unsigned)p->xy_segs, (unsigned)p->n[2]),
-                       dim3(kLanes * kXYWaves), ring, s, PX, PY, (const V *)PX.psi, (V *)PY.out,
-                       (const V *)PX.tab, (const V *)PY.tab);
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <typename R, int MODE, int XFLAGS, int Q>
-static hipError_t launch_xy_q(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s)
-{
-    switch (p->ax[1].D) {
-    case 2: launch_xy_dw<R, MODE, XFLAGS, Q, 2>(p, PX, PY, s); break;
-    case 3: launch_xy_dw<R, MODE, XFLAGS, Q, 3>(p, PX, PY, s); break;
-    case 4: launch_xy_dw<R, MODE, XFLAGS, Q, 4>(p, PX, PY, s); break;
-    default: return hipErrorInvalidValue;
+// y solver of one column (one lane) with its elimination window in registers:
+// the window holds the eliminated values of the last DW + 1 blocks of four rows,
+// and the block loop is unrolled by DW + 1 so block j's values live in slot
+// u = (j - j0) mod (DW + 1), a compile-time index in every unrolled copy.
+// The arithmetic is WindowSweep::process's (same order, same table rows), only
+// the ring moved from LDS to registers.
+template <typename R, int MODE, int DW> struct YRegSolver {
+    using V = typename CT<R>::V;
+    static constexpr int B = kXYWaves;
+    cp<R> d[DW + 1][B];
+    cp<R> um1, u0, dprev;
+    int o_lo, o_hi;
+    int64_t base, stride, n;
+
+    // block j (rows jB .. jB+3 in v), stored in slot U; writes output block j - DW
+    template <int U>
+    __device__ __forceinline__ void process(const cp<R> (&v)[B], int j, const V *__restrict__ tab, V *dst)
+    {
+        static_for<B>([&](auto K) {  // eliminated point p = jB + K - 1, table row q = p + 1
+            constexpr int k = decltype(K)::value;
+            const int64_t q = (int64_t)j * B + k;
+            const cp<R> rhs = cn_rhs<MODE, R>(um1, u0, v[k], tab[3 * q + 1], tab[3 * q + 2]);
+            const cp<R> e = cn_elim<MODE, R>(rhs, dprev, tab[3 * q]);
+            d[U][k] = e;
+            dprev = e;
+            um1 = u0;
+            u0 = v[k];
+        });
+        const int o = j - DW;
+        if (o < o_lo || o >= o_hi) return;  // uniform
+        const int64_t ob = (int64_t)o * B;
+        cp<R> x = {R(0), R(0)};
+        cp<R> out[B];
+        // q = t + 1 from ob + (DW+1)B - 1 down to ob + 1; block (q - ob) / B of the
+        // window is slot (U + 1 + (q - ob) / B) mod (DW + 1).  Expanded as a fold
+        // so every slot index is a constant (a rolled loop would put d in scratch).
+        constexpr int L = (DW + 1) * B - 1;
+        static_for<L>([&](auto I) {
+            constexpr int i = L - decltype(I)::value;
+            x = cn_back<MODE, R>(d[(U + 1 + i / B) % (DW + 1)][i % B], tab[3 * (ob + i)], x);
+            if constexpr (i <= B) out[i - 1] = x;
+        });
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int64_t t = ob + k;
+            if (t < n) dst[base + t * stride] = to_v<V>(out[k]);
+        }
     }
+};
+
+template <typename R, int MODE, int XFLAGS, int Q, int DW>
+__global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams PX, SweepParams PY,
+                                                                    const typename CT<R>::V *src,
+                                                                    typename CT<R>::V *dst,
+                                                                    const typename CT<R>::V *__restrict__ tabx,
+                                                                    const typename CT<R>::V *__restrict__ taby)
+{
+    using V = typename CT<R>::V;
+    constexpr int B = kXYWaves;
+    __shared__ V tile[2][B][kLanes * Q];
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int64_t nx = PX.n, ny = PY.n;
+    const int64_t k = blockIdx.y;
+    const int cw = (int)(nx / kLanes);
+    const cp<R> zero = {R(0), R(0)};
+
+    YRegSolver<R, MODE, DW> Y;
+    {
+        const int nb = PY.nblocks, segs = (int)gridDim.x, sg = (int)blockIdx.x;
+        Y.o_lo = (int)((int64_t)sg * nb / segs);
+        Y.o_hi = (int)((int64_t)(sg + 1) * nb / segs);
+        Y.um1 = Y.u0 = Y.dprev = zero;
+        Y.base = (int64_t)(w * kLanes + lane) + nx * ny * k;
+        Y.stride = nx;
+        Y.n = ny;
+    }
+    const int j0 = Y.o_lo - DW > 0 ? Y.o_lo - DW : 0;
+    const int j1 = Y.o_hi + DW;  // exclusive, uniform over the workgroup
+
+    const int S = PX.scan_steps;
+    XConsts<R, Q, kXYMaxScan> KX;
+    x_consts_load<R, Q, kXYMaxScan>(PX, tabx, (const V *)PX.xmul, lane, KX);
+    const double renorm = (XFLAGS & F_RENORM) ? 1.0 / sqrt(PX.dV * PX.norm_total[0]) : 1.0;
+
+    // x-solve this wavefront's row of block j into tile[j & 1] (rows past the
+    // plane, or blocks past j1, are zero rows), from values `in` loaded earlier
+    auto x_row = [&](int j, V (&in)[Q]) {
+        V *row = tile[j & 1][w];
+        const int64_t y = (int64_t)j * B + w;
+        if (j < j1 && y < ny) {  // uniform over the wavefront
+            cp<R> u[Q];
+            LineCtx<R> L = line_ctx_of<R>(PX, y + ny * k);
+            if (XFLAGS & F_RENORM) L.scale = renorm;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int64_t q = lane + kLanes * i;
+                u[i] = from_v<R>(in[i]);
+                if ((XFLAGS & F_FUSE_N) && q < nx) u[i] = potential_substep<R, MODE, XFLAGS>(u[i], q, PX, L);
+            }
+            if (Q > 1) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) row[xy_slot(lane + kLanes * i)] = to_v<V>(u[i]);
+                wave_lds_sync();
+#pragma unroll
+                for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot(lane * Q + i)]);
+                wave_lds_sync();
+            }
+            x_line_solve<R, MODE, Q, kXYMaxScan>(PX, KX, S, lane, u);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(u[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(zero);
+        }
+    };
+
+    V ahead[Q];
+    xy_load_row<R, Q>(src, j0, j1, w, k, nx, ny, lane, ahead);
+    x_row(j0, ahead);
+    xy_load_row<R, Q>(src, j0 + 1, j1, w, k, nx, ny, lane, ahead);
+    __syncthreads();
+    int u = 0;  // window slot of block j: (j - j0) mod (DW + 1)
+#pragma unroll 1
+    for (int j = j0; j < j1; ++j) {
+        // the next block's x solve (its rows were loaded a block ago), then the
+        // request for the rows after it
+        x_row(j + 1, ahead);
+        xy_load_row<R, Q>(src, j + 2, j1, w, k, nx, ny, lane, ahead);
+        if (w < cw) {
+            cp<R> v[B];
+#pragma unroll
+            for (int r = 0; r < B; ++r) v[r] = from_v<R>(tile[j & 1][r][xy_slot(w * kLanes + lane)]);
+            // one copy of the y step per window slot, so the slot index is a constant
+            static_for<DW + 1>([&](auto U) {
+                if (u == decltype(U)::value) Y.template process<decltype(U)::value>(v, j, taby, dst);
+            });
+        }
+        u = u == DW ? 0 : u + 1;
+        __syncthreads();
+    }
+}
+
+// Launch the fused kernel of the plan's shape, or (occ != nullptr) only report
+// how many of its workgroups one CU holds at once.
+template <typename R, int MODE, int XFLAGS, int Q, int DW>
+static hipError_t launch_xy_dw(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s,
+                               int variant, int *occ)
+{
+    using V = typename CT<R>::V;
+    const dim3 grid((unsigned)p->xy_segs, (unsigned)p->n[2]), block(kLanes * kXYWaves);
+    if (variant == 2) {  // elimination window in registers, double-buffered tile
+        const auto kern = k_sweep_xy_reg<R, MODE, XFLAGS, Q, DW>;
+        if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, (int)block.x, 0);
+        hipLaunchKernelGGL(kern, grid, block, 0, s, PX, PY, (const V *)PX.psi, (V *)PY.out, (const V *)PX.tab,
+                           (const V *)PY.tab);
+        return hipGetLastError();
+    }
+    const auto kern = k_sweep_xy<R, MODE, XFLAGS, Q, DW>;
+    const size_t ring = (size_t)kXYWaves * (size_t)p->ax[1].L * kLanes * sizeof(V);
+    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, (int)block.x, ring);
+    hipLaunchKernelGGL(kern, grid, block, ring, s, PX, PY, (const V *)PX.psi, (V *)PY.out, (const V *)PX.tab,
+                       (const V *)PY.tab);
     return hipGetLastError();
 }
 
+template <typename R, int MODE, int XFLAGS, int Q>
+static hipError_t launch_xy_q(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s,
+                              int variant, int *occ)
+{
+    switch (p->ax[1].D) {
+    case 2: return launch_xy_dw<R, MODE, XFLAGS, Q, 2>(p, PX, PY, s, variant, occ);
+    case 3: return launch_xy_dw<R, MODE, XFLAGS, Q, 3>(p, PX, PY, s, variant, occ);
+    case 4: return launch_xy_dw<R, MODE, XFLAGS, Q, 4>(p, PX, PY, s, variant, occ);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, int MODE, int XFLAGS>
-static hipError_t launch_xy_flags(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s)
+static hipError_t launch_xy_flags(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, hipStream_t s,
+                                  int variant, int *occ)
 {
     switch (p->ax[0].xq) {
-    case 2: return launch_xy_q<R, MODE, XFLAGS, 2>(p, PX, PY, s);
-    case 4: return launch_xy_q<R, MODE, XFLAGS, 4>(p, PX, PY, s);
+    case 2: return launch_xy_q<R, MODE, XFLAGS, 2>(p, PX, PY, s, variant, occ);
+    case 4: return launch_xy_q<R, MODE, XFLAGS, 4>(p, PX, PY, s, variant, occ);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R>
 static hipError_t launch_xy_r(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, int flags,
-                              hipStream_t s)
+                              hipStream_t s, int variant, int *occ)
 {
     if (p->mode == GP_IMAG)
-        return (flags & F_RENORM) ? launch_xy_flags<R, GP_IMAG, F_FUSE_N | F_RENORM>(p, PX, PY, s)
-                                  : launch_xy_flags<R, GP_IMAG, F_FUSE_N>(p, PX, PY, s);
-    return launch_xy_flags<R, GP_REAL, F_FUSE_N>(p, PX, PY, s);
+        return (flags & F_RENORM) ? launch_xy_flags<R, GP_IMAG, F_FUSE_N | F_RENORM>(p, PX, PY, s, variant, occ)
+                                  : launch_xy_flags<R, GP_IMAG, F_FUSE_N>(p, PX, PY, s, variant, occ);
+    return launch_xy_flags<R, GP_REAL, F_FUSE_N>(p, PX, PY, s, variant, occ);
+}
+
+hipError_t xy_dispatch(const gp_plan *p, const SweepParams &PX, const SweepParams &PY, int flags, hipStream_t s,
+                       int variant, int *occ)
+{
+    return p->prec == GP_C128 ? launch_xy_r<double>(p, PX, PY, flags, s, variant, occ)
+                              : launch_xy_r<float>(p, PX, PY, flags, s, variant, occ);
 }
 
 }  // namespace
 
-size_t xy_lds_bytes(const gp_plan *p)
+size_t xy_lds_bytes(const gp_plan *p, int variant)
 {
     const size_t eb = elem_bytes(p->prec);
-    return (size_t)kXYWaves * kLanes * (size_t)p->ax[0].xq * eb +
-           (size_t)kXYWaves * (size_t)p->ax[1].L * kLanes * eb;
+    const size_t tile = (size_t)kXYWaves * kLanes * (size_t)p->ax[0].xq * eb;
+    if (variant == 2) return 2 * tile;
+    return tile + (size_t)kXYWaves * (size_t)p->ax[1].L * kLanes * eb;
 }
 
-int xy_choose_segments(const gp_plan *p, int64_t max_lds)
+int xy_choose_segments(const gp_plan *p, int variant, int64_t max_lds)
 {
     if (p->ndim != 3) return 0;
     const AxisPlan &X = p->ax[0], &Y = p->ax[1];
@@ -193,14 +371,20 @@ int xy_choose_segments(const gp_plan *p, int64_t max_lds)
     if (X.scan_steps > kXYMaxScan) return 0;
     if (p->n[0] % kLanes != 0 || p->n[0] > (int64_t)kLanes * X.xq) return 0;
     if (Y.K < 0 || Y.B != 4 || Y.D < 2 || Y.D > 4) return 0;
-    if ((int64_t)xy_lds_bytes(p) > max_lds) return 0;
-    // about two workgroups per CU of a 256-CU device, each segment at least
-    // four windows long
+    if ((int64_t)xy_lds_bytes(p, variant) > max_lds) return 0;
+    // as many workgroups as the device holds at once (its CUs times what one CU
+    // holds of this kernel), in segments of at least four windows; segments
+    // beyond that would only queue and repeat their warm-up rows
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const SweepParams none{};
+    if (xy_dispatch(p, none, none, F_FUSE_N, nullptr, variant, &per_cu) != hipSuccess || per_cu < 1) per_cu = 2;
     const int64_t nb = (p->n[1] + 3) / 4;
-    int segs = (int)((512 + p->n[2] - 1) / p->n[2]);
-    const int most = (int)std::max<int64_t>(1, nb / (4 * (Y.D + 1)));
-    if (segs > most) segs = most;
-    return segs < 1 ? 1 : segs;
+    int64_t segs = (int64_t)cus * per_cu / p->n[2];
+    const int64_t most = std::max<int64_t>(1, nb / (4 * (Y.D + 1)));
+    segs = std::min(segs, most);
+    return (int)std::max<int64_t>(1, segs);
 }
 
 hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s)
@@ -208,8 +392,7 @@ hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t 
     SweepParams PX = make_sweep_params(p, 0, src, nullptr, false, step_index, nullptr);
     SweepParams PY = make_sweep_params(p, 1, nullptr, dst, false, step_index, nullptr);
     timing_begin(p, K_SWEEP_XY, s);
-    const hipError_t e = p->prec == GP_C128 ? launch_xy_r<double>(p, PX, PY, flags, s)
-                                            : launch_xy_r<float>(p, PX, PY, flags, s);
+    const hipError_t e = xy_dispatch(p, PX, PY, flags, s, p->xy_variant, nullptr);
     timing_end(p, s);
     return e;
 }

@@ -1,6 +1,7 @@
-"""Fused x+y sweep of 3D steps: against the FP64 oracle, against the same plan
-with the sweeps run as separate kernels, over x extents 128/192/256, ragged y
-extents and several row segments per plane, in both modes and precisions."""
+"""Fused x+y sweep of 3D steps (both variants: the y window in LDS, 1, and in
+registers, 2): against the FP64 oracle, against the same plan with the sweeps
+run as separate kernels, over x extents 128/192/256, ragged y extents and
+several row segments per plane, in both modes and precisions."""
 import sys
 
 import numpy as np
@@ -48,14 +49,16 @@ def initial(n, dx, omega, seed):
     return inputs.gaussian(n, dx, omega) + 0.05 * inputs.random_field(tuple(n[::-1]), seed)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])))
-def test_fused_step_matches_oracle_and_separate_sweeps(gp, case, mode):
+def test_fused_step_matches_oracle_and_separate_sweeps(gp, case, mode, variant):
     n, dx, dt, omega, g, steps, multi = case
     psi0 = initial(n, dx, omega, 7)
     plan = gp.Plan(n, dx, dt, mode, omega, g)
+    plan.set_xy_fusion(variant)
     info = plan.info()
-    say(f"fused n={n} mode={mode} info={info}")
+    say(f"fused n={n} mode={mode} variant={variant} info={info}")
     assert info["xy_fused"] >= 1
     assert (info["xy_fused"] > 1) == multi
     psi = to_dev(psi0)
@@ -75,11 +78,14 @@ def test_fused_step_matches_oracle_and_separate_sweeps(gp, case, mode):
         assert abs(o[k] - r[k]) <= 1e-12 * abs(r[k]), k
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_fused_step_fp32(gp, mode):
+def test_fused_step_fp32(gp, mode, variant):
     n, dx, dt, omega, g, steps, _ = CASES[1]
     psi0 = initial(n, dx, omega, 8)
     plan = gp.Plan(n, dx, dt, mode, omega, g, gp.GP_C64)
+    plan.set_xy_fusion(variant)
+    say(f"fused fp32 n={n} mode={mode} variant={variant} info={plan.info()}")
     assert plan.info()["xy_fused"] >= 1
     psi = to_dev(psi0.astype(np.complex64))
     plan.step(psi, steps)
@@ -102,14 +108,15 @@ def test_fused_headline_grid_matches_separate_sweeps(gp):
     w = inputs.HEADLINE_3D
     psi0 = to_dev(inputs.headline_initial())
     out = []
-    for fuse in (True, False):
+    for fuse in (2, 1, 0):
         psi = psi0.clone()
         for mode in (gp.GP_IMAG, gp.GP_REAL):
             plan = gp.Plan(w.n, w.dx, w.dt, mode, w.omega, w.g)
             plan.set_xy_fusion(fuse)
-            assert (plan.info()["xy_fused"] > 0) == fuse
+            assert (plan.info()["xy_fused"] > 0) == (fuse > 0)
             plan.step(psi, 3)
         out.append(psi)
-    d = float((out[0] - out[1]).abs().max() / out[1].abs().max())
-    say(f"256^3 fused vs separate: {d:.2e}")
-    assert d <= 1e-13
+    for k, fuse in enumerate((2, 1)):
+        d = float((out[k] - out[2]).abs().max() / out[2].abs().max())
+        say(f"256^3 fused variant {fuse} vs separate: {d:.2e}")
+        assert d <= 1e-13
