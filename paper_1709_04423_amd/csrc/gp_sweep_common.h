@@ -241,6 +241,69 @@ __device__ __forceinline__ cp<R> potential_substep(cp<R> u, int64_t q, const Swe
     return {u.re * f, u.im * f};
 }
 
+// The potential substep on Q values of one line, at points q0 + qs i, with the
+// same arithmetic as potential_substep.  The series branch is taken for all Q
+// values together, with no per-value branch, so their dependency chains
+// interleave; values whose angle exceeds the series range (rare; the wavefront
+// checks once) are redone with the library functions.
+template <typename R, int MODE, int FLAGS, int Q>
+__device__ __forceinline__ void potential_substep_q(cp<R> (&u)[Q], int q0, int qs, const SweepParams &P,
+                                                    const LineCtx<R> &L)
+{
+    R th[Q];
+    bool big = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (FLAGS & F_RENORM) {
+            u[i].re = R((double)u[i].re * L.scale);
+            u[i].im = R((double)u[i].im * L.scale);
+        }
+        const R x = R(((double)(q0 + qs * i) + P.x0[0]) * P.dx[0]);
+        th[i] = R(P.dt) * (L.vperp + L.hw0 * x * x + R(P.g) * (u[i].re * u[i].re + u[i].im * u[i].im));
+        big |= !(fabs(th[i]) <= R(0.125));
+    }
+    using T = Taylor<R>;
+    if (MODE == GP_REAL) {
+        R sn[Q], h[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R t = th[i], t2 = t * t;
+            if (sizeof(R) == 8) {
+                sn[i] = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * (T::s7 + t2 * (T::s9 + t2 * T::s11))));
+                h[i] = t2 * (T::h2 + t2 * (T::h4 + t2 * (T::h6 + t2 * (T::h8 + t2 * T::h10))));
+            } else {
+                sn[i] = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * T::s7));
+                h[i] = t2 * (T::h2 + t2 * (T::h4 + t2 * T::h6));
+            }
+        }
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (!(fabs(th[i]) <= R(0.125))) phase_r(th[i], &sn[i], &h[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) u[i] = rotate(u[i], sn[i], h[i], R(1));
+        return;
+    }
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R t = -th[i];
+        if (sizeof(R) == 8)
+            f[i] = 1.0 + t * (1.0 + t * (T::e2 + t * (T::e3 + t * (T::e4 + t * (T::e5 + t * (T::e6 + t * (T::e7 +
+                   t * (T::e8 + t * (T::e9 + t * (T::e10 + t * T::e11))))))))));
+        else
+            f[i] = R(1) + t * (R(1) + t * (T::e2 + t * (T::e3 + t * (T::e4 + t * (T::e5 + t * T::e6)))));
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (!(fabs(th[i]) <= R(0.125))) f[i] = exp_r(-th[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) u[i] = {u[i].re * f[i], u[i].im * f[i]};
+}
+
 // Adjoint of the potential substep at point t: lam (gradient of its output)
 // -> gradient of its input; accumulates the schedule and g gradient sums.
 template <typename R, int MODE, int FLAGS, typename V>

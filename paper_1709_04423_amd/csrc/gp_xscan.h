@@ -274,11 +274,8 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
             const int64_t nl = line + 1;
             x_load_line<R, Q>(src, nl, P.nlines, n, lane, nxt);
         }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int64_t q = lane + kLanes * i;
-            if ((FLAGS & F_FUSE_N) && q < n) u[i] = potential_substep<R, MODE, FLAGS>(u[i], q, P, L);
-        }
+        // points past the line's end are zeros and stay zeros
+        if (FLAGS & F_FUSE_N) potential_substep_q<R, MODE, FLAGS, Q>(u, lane, kLanes, P, L);
         if (Q > 1) {  // coalesced -> Q consecutive points per lane
 #pragma unroll
             for (int i = 0; i < Q; ++i) xl[pad(lane + kLanes * i)] = to_v<V>(u[i]);

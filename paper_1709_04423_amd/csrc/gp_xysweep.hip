@@ -100,11 +100,8 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
             if (y < ny) {  // uniform over the wavefront
                 LineCtx<R> L = line_ctx_of<R>(PX, y + ny * k);
                 if (XFLAGS & F_RENORM) L.scale = renorm;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int64_t q = lane + kLanes * i;
-                    if ((XFLAGS & F_FUSE_N) && q < nx) u[i] = potential_substep<R, MODE, XFLAGS>(u[i], q, PX, L);
-                }
+                // points past the row's end are zeros and stay zeros
+                if (XFLAGS & F_FUSE_N) potential_substep_q<R, MODE, XFLAGS, Q>(u, lane, kLanes, PX, L);
                 if (Q > 1) {  // coalesced -> Q consecutive points per lane
 #pragma unroll
                     for (int i = 0; i < Q; ++i) row[xy_slot(lane + kLanes * i)] = to_v<V>(u[i]);
@@ -242,11 +239,9 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
             LineCtx<R> L = line_ctx_of<R>(PX, y + ny * k);
             if (XFLAGS & F_RENORM) L.scale = renorm;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const int64_t q = lane + kLanes * i;
-                u[i] = from_v<R>(in[i]);
-                if ((XFLAGS & F_FUSE_N) && q < nx) u[i] = potential_substep<R, MODE, XFLAGS>(u[i], q, PX, L);
-            }
+            for (int i = 0; i < Q; ++i) u[i] = from_v<R>(in[i]);
+            // points past the row's end are zeros and stay zeros
+            if (XFLAGS & F_FUSE_N) potential_substep_q<R, MODE, XFLAGS, Q>(u, lane, kLanes, PX, L);
             if (Q > 1) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) row[xy_slot(lane + kLanes * i)] = to_v<V>(u[i]);
