@@ -560,6 +560,14 @@ static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n
             else
                 x_scan_setup<float>(A, cs[a], mode);
             if (A.xq > 0 && A.npad < (int64_t)A.xq * kLanes) A.npad = (int64_t)A.xq * kLanes;
+        } else if (a == 1 && ndim == 2 && A.n <= (int64_t)kColMaxQ * kLanes) {
+            // a 2D grid's y lines are too few for the windowed solver to fill
+            // the device: one wavefront per line with the scan solver instead
+            if (prec == GP_C128)
+                x_scan_setup<double>(A, cs[a], mode);
+            else
+                x_scan_setup<float>(A, cs[a], mode);
+            if (A.xq > 0 && A.npad < (int64_t)A.xq * kLanes) A.npad = (int64_t)A.xq * kLanes;
         }
     }
 
@@ -576,11 +584,11 @@ static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n
     for (int a = radial ? 1 : 0; a < ndim && st == GP_OK; ++a) {
         st = upload_table(p, p->ax[a], cs[a], false, &p->ax[a].d_tab);
         if (st == GP_OK && mode == GP_REAL) st = upload_table(p, p->ax[a], cs[a], true, &p->ax[a].d_tab_adj);
-        if (st == GP_OK && a == 0 && p->ax[0].xq > 0) {
+        if (st == GP_OK && p->ax[a].xq > 0) {
             for (int cj = 0; cj < (mode == GP_REAL ? 2 : 1) && st == GP_OK; ++cj) {
-                void **dst = cj ? &p->ax[0].d_xmul_adj : &p->ax[0].d_xmul;
-                st = prec == GP_C128 ? upload_x_multipliers<double>(p, p->ax[0], cs[0], cj != 0, dst)
-                                     : upload_x_multipliers<float>(p, p->ax[0], cs[0], cj != 0, dst);
+                void **dst = cj ? &p->ax[a].d_xmul_adj : &p->ax[a].d_xmul;
+                st = prec == GP_C128 ? upload_x_multipliers<double>(p, p->ax[a], cs[a], cj != 0, dst)
+                                     : upload_x_multipliers<float>(p, p->ax[a], cs[a], cj != 0, dst);
             }
         }
     }
@@ -647,8 +655,8 @@ gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info)
     for (int a = 0; a < 3; ++a) {
         info->n[a] = a < plan->ndim ? plan->n[a] : 1;
         info->window[a] = a < plan->ndim ? plan->ax[a].K : 0;
-        if (a == 0 && plan->ax[0].xq > 0)  // scan kernel: a carry reaches Q 2^S points (S = 6: whole line, exact)
-            info->window[0] = plan->ax[0].scan_steps >= 6 ? -1 : plan->ax[0].xq * (1 << plan->ax[0].scan_steps) - 1;
+        if (a < plan->ndim && plan->ax[a].xq > 0)  // scan solver: a carry reaches Q 2^S points (S = 6: whole line)
+            info->window[a] = plan->ax[a].scan_steps >= 6 ? -1 : plan->ax[a].xq * (1 << plan->ax[a].scan_steps) - 1;
         info->rho[a] = a < plan->ndim ? plan->ax[a].rho : 0.0;
         info->window_bound[a] = a < plan->ndim ? plan->ax[a].bound : 0.0;
     }

@@ -176,6 +176,11 @@ hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
 inline double *norm_partials(gp_plan *p, int64_t step) { return p->d_norm + (step & 1) * p->n_norm; }
 inline double *norm_total(gp_plan *p, int64_t step) { return p->d_norm + 2 * p->n_norm + (step & 1); }
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
+// Strided axis solved with the scan solver (AxisPlan::xq > 0 on an axis other
+// than 0): flags 0 or F_NORM_OUT.
+hipError_t launch_col_scan(const gp_plan *p, int axis, const SweepParams &P, int flags, const void *tab,
+                           hipStream_t s);
+constexpr int kColMaxQ = 8;  // longest strided line of the scan solver: 64 kColMaxQ points
 // Fused x and y sweeps of a 3D step (src -> dst, x flags as for the x sweep).
 hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
 size_t xy_lds_bytes(const gp_plan *p, int variant);

@@ -16,7 +16,7 @@ int64_t sweep_groups(const gp_plan *p, int axis)
 {
     if (axis == 0 && p->geom != GP_CARTESIAN) return radial_line_groups(p);
     const AxisPlan &A = p->ax[axis];
-    if (axis == 0 && A.xq > 0) return (A.nlines + kXWavesPerGroup * A.xlpw - 1) / (kXWavesPerGroup * A.xlpw);
+    if (A.xq > 0) return (A.nlines + kXWavesPerGroup * A.xlpw - 1) / (kXWavesPerGroup * A.xlpw);
     const int64_t g = (A.nlines + kLanes - 1) / kLanes;
     return A.K < 0 ? g : g * A.segs;
 }
@@ -91,6 +91,12 @@ hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int fl
     if (axis == 0 && A.xq > 0) {  // one wavefront per x line
         timing_begin(p, (flags & F_ADJ_N) ? K_ADJ_X : K_SWEEP_X, s);
         hipError_t e = launch_x_scan(p, P, flags, tab, s);
+        timing_end(p, s);
+        return e;
+    }
+    if (A.xq > 0) {  // strided axis, one wavefront per line
+        timing_begin(p, kind, s);
+        hipError_t e = launch_col_scan(p, axis, P, flags, tab, s);
         timing_end(p, s);
         return e;
     }

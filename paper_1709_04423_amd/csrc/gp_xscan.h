@@ -305,4 +305,59 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     }
 }
 
+// The same scan solver on a strided axis (a 2D grid's y lines): one wavefront
+// per line, lane L loading points L Q .. L Q + Q - 1 straight into the
+// solver's layout (no transpose), at stride P.stride from the line's base.
+// Each load touches one point of 64 rows; the wavefronts of a workgroup take
+// neighbouring lines at the same time (line first + w + lstep li for
+// wavefront w), so they share the cache lines of those rows.  No potential
+// substep (the x sweep carries it); F_NORM_OUT sums |u'|^2 into nacc.
+template <typename R, int Q>
+__device__ __forceinline__ void col_load_line(const typename CT<R>::V *src, const SweepParams &P, int64_t line,
+                                              int lane, typename CT<R>::V (&dst)[Q])
+{
+    const int64_t lc = line < P.nlines ? line : P.nlines - 1;
+    const int64_t base = (lc % P.m1) * P.s1 + (lc / P.m1) * P.s2;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t q = (int64_t)lane * Q + i;
+        dst[i] = src[base + (q < P.n ? q : P.n - 1) * P.stride];
+    }
+}
+
+template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
+__device__ __forceinline__ void col_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
+                                              typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
+                                              int64_t first, int count, int64_t lstep, double &nacc)
+{
+    using V = typename CT<R>::V;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int64_t n = P.n;
+    const cp<R> zero = {R(0), R(0)};
+    XConsts<R, Q, SMAX> K;
+    x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+    V nxt[Q];
+    col_load_line<R, Q>(src, P, first, lane, nxt);
+#pragma unroll 1
+    for (int li = 0; li < count; ++li) {
+        const int64_t line = first + li * lstep;
+        if (line >= P.nlines) break;  // uniform across the wavefront
+        const int64_t base = (line % P.m1) * P.s1 + (line / P.m1) * P.s2;
+        cp<R> u[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) u[i] = (int64_t)lane * Q + i < n ? from_v<R>(nxt[i]) : zero;
+        if (li + 1 < count) col_load_line<R, Q>(src, P, line + lstep, lane, nxt);
+        x_line_solve<R, MODE, Q, SMAX>(P, K, P.scan_steps, lane, u);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t q = (int64_t)lane * Q + i;
+            if (q < n) {
+                if (FLAGS & F_NORM_OUT)
+                    nacc += (double)u[i].re * (double)u[i].re + (double)u[i].im * (double)u[i].im;
+                dst[base + q * P.stride] = to_v<V>(u[i]);
+            }
+        }
+    }
+}
+
 }  // namespace gp

@@ -97,6 +97,80 @@ static hipError_t launch_x_mode(const SweepParams &P, int flags, int Q, const vo
     }
 }
 
+// Strided axis with the scan solver: workgroup b's wavefront w takes lines
+// b 4 lpw + w + 4 li (li < lpw), so its four wavefronts work on neighbouring
+// lines at every moment; one FP64 norm partial per workgroup (F_NORM_OUT).
+template <typename R, int MODE, int FLAGS, int Q, int SMAX>
+__global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_col_scan(SweepParams P, const typename CT<R>::V *src,
+                                                                     typename CT<R>::V *dst,
+                                                                     const typename CT<R>::V *__restrict__ tab)
+{
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = threadIdx.x / kLanes;
+    double nacc = 0.0;
+    col_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, (int64_t)blockIdx.x * kXWaves * P.xlpw + wave, P.xlpw,
+                                           kXWaves, nacc);
+    if (FLAGS & F_NORM_OUT) {
+        __shared__ double red[kXWaves];
+        nacc = wave_sum(nacc);
+        if (lane == 0) red[wave] = nacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            for (int w = 0; w < kXWaves; ++w) a += red[w];
+            P.norm_out[blockIdx.x] = a;
+        }
+    }
+}
+
+template <typename R, int MODE, int FLAGS, int Q>
+static void launch_col_q(const SweepParams &P, const void *tab, hipStream_t s)
+{
+    using V = typename CT<R>::V;
+    const int64_t per_group = (int64_t)kXWaves * P.xlpw;
+    const unsigned grid = (unsigned)((P.nlines + per_group - 1) / per_group);
+    if (P.scan_steps <= 3)
+        hipLaunchKernelGGL((k_sweep_col_scan<R, MODE, FLAGS, Q, 3>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
+                           (const V *)P.psi, (V *)P.out, (const V *)tab);
+    else
+        hipLaunchKernelGGL((k_sweep_col_scan<R, MODE, FLAGS, Q, 6>), dim3(grid), dim3(kLanes * kXWaves), 0, s, P,
+                           (const V *)P.psi, (V *)P.out, (const V *)tab);
+}
+
+template <typename R, int MODE, int FLAGS>
+static hipError_t launch_col_flags(const SweepParams &P, int Q, const void *tab, hipStream_t s)
+{
+    switch (Q) {
+    case 1: launch_col_q<R, MODE, FLAGS, 1>(P, tab, s); break;
+    case 2: launch_col_q<R, MODE, FLAGS, 2>(P, tab, s); break;
+    case 4: launch_col_q<R, MODE, FLAGS, 4>(P, tab, s); break;
+    case 8: launch_col_q<R, MODE, FLAGS, 8>(P, tab, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int MODE>
+static hipError_t launch_col_mode(const SweepParams &P, int flags, int Q, const void *tab, hipStream_t s)
+{
+    switch (flags) {
+    case 0: return launch_col_flags<R, MODE, 0>(P, Q, tab, s);
+    case F_NORM_OUT: return launch_col_flags<R, MODE, F_NORM_OUT>(P, Q, tab, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_col_scan(const gp_plan *p, int axis, const SweepParams &P, int flags, const void *tab,
+                           hipStream_t s)
+{
+    const int Q = p->ax[axis].xq;
+    if (p->prec == GP_C128)
+        return p->mode == GP_IMAG ? launch_col_mode<double, GP_IMAG>(P, flags, Q, tab, s)
+                                  : launch_col_mode<double, GP_REAL>(P, flags, Q, tab, s);
+    return p->mode == GP_IMAG ? launch_col_mode<float, GP_IMAG>(P, flags, Q, tab, s)
+                              : launch_col_mode<float, GP_REAL>(P, flags, Q, tab, s);
+}
+
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s)
 {
     const int Q = p->ax[0].xq;

@@ -368,8 +368,9 @@ int xy_choose_segments(const gp_plan *p, int variant, int64_t max_lds)
     if (Y.K < 0 || Y.B != 4 || Y.D < 2 || Y.D > 4) return 0;
     if ((int64_t)xy_lds_bytes(p, variant) > max_lds) return 0;
     // as many workgroups as the device holds at once (its CUs times what one CU
-    // holds of this kernel), in segments of at least four windows; segments
-    // beyond that would only queue and repeat their warm-up rows
+    // holds of this kernel), in segments of at least two windows: an idle CU
+    // costs more than the warm-up rows a segment repeats, and workgroups beyond
+    // what the device holds would only queue
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
         cus = 256;
@@ -377,7 +378,7 @@ int xy_choose_segments(const gp_plan *p, int variant, int64_t max_lds)
     if (xy_dispatch(p, none, none, F_FUSE_N, nullptr, variant, &per_cu) != hipSuccess || per_cu < 1) per_cu = 2;
     const int64_t nb = (p->n[1] + 3) / 4;
     int64_t segs = (int64_t)cus * per_cu / p->n[2];
-    const int64_t most = std::max<int64_t>(1, nb / (4 * (Y.D + 1)));
+    const int64_t most = std::max<int64_t>(1, nb / (2 * (Y.D + 1)));
     segs = std::min(segs, most);
     return (int)std::max<int64_t>(1, segs);
 }

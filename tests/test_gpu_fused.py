@@ -38,9 +38,9 @@ def max_rel(got, ref):
 
 CASES = [
     # (n (x first), dx, dt, omega, g, steps, expected row segments > 1)
-    ((128, 48, 20), (0.2, 0.2, 0.25), 1e-3, (1.0, 1.5, 2.0), 50.0, 3, False),
+    ((128, 22, 20), (0.2, 0.2, 0.25), 1e-3, (1.0, 1.5, 2.0), 50.0, 3, False),
     ((192, 201, 8), (0.1, 0.1, 0.3), 1e-3, (1.0, 1.2, 2.0), 80.0, 3, True),
-    ((256, 96, 6), (0.05, 0.1, 0.3), 5e-4, (1.0, 2.0, 3.0), 200.0, 2, False),
+    ((256, 42, 6), (0.05, 0.1, 0.3), 5e-4, (1.0, 2.0, 3.0), 200.0, 2, False),
     ((256, 130, 3), (0.05, 0.08, 0.4), 5e-4, (1.0, 1.0, 1.0), 20.0, 2, True),
 ]
 
