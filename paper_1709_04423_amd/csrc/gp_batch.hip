@@ -5,7 +5,10 @@
 // batch adds per-problem sweep parameters in device memory and lists of
 // wavefront-sized work items:
 //   x items  (problem, first line, count): count x lines, one wavefront (scan solver),
-//   y items  (problem, 64-column group, segment): one wavefront (windowed solver).
+//   y items  (problem, first line, count) for y lines of up to 512 points: count
+//            lines, one wavefront (the same scan solver on the strided axis), or
+//            (problem, 64-column group, segment) for longer ones: one wavefront
+//            (windowed solver).
 // A step is the x items of every problem followed by the y items of every
 // problem.  Two ways to run nsteps steps:
 //   - phased: two launches per step (all x items, then all y items);
@@ -39,10 +42,10 @@ namespace gp {
 
 struct BatchItem {
     int prob;
-    int seg;    // y: segment index; x: unused
-    int segs;   // y: segments of this problem's lines; x: unused
-    int count;  // x: lines in the item; y: unused
-    int64_t first;  // x: first line; y: 64-column group
+    int seg;    // windowed y: segment index; scan y: the item's norm partial slot; x: unused
+    int segs;   // windowed y: segments of this problem's lines; scan y and x: 0
+    int count;  // x and scan y: lines in the item; windowed y: unused
+    int64_t first;  // x and scan y: first line; windowed y: 64-column group
 };
 
 // Counters of the persistent launch: queue head, error flag, then per problem
@@ -77,6 +80,8 @@ struct gp_batch {
     int64_t *d_nparts = nullptr;   // y partials per problem (imaginary-time norm)
     size_t lds_wave = 0;           // ring bytes of one y wavefront (largest problem)
     int qmax = 1;                  // largest x points per lane over the problems
+    int qmax_y = 0;                // largest y points per lane of the scan-solved y lines (0: none)
+    int smax = 6;                  // most scan steps of any scan-solved line: 3 or 6 (sizes the solvers' registers)
     std::vector<const void *> bound; // psi pointers the device parameters were built for
     int bound_cfg_lines = -1, bound_cfg_ysegs = -1;
 };
@@ -87,36 +92,56 @@ static __device__ __forceinline__ int wave_first_lane_i(int v) { return __builti
 
 // ------------------------------------------------------------ item bodies
 
-// QMAX: the largest points-per-lane of the batch's x lines; only the solver
-// variants up to it are compiled into a kernel (their registers would be
-// allocated even when not taken).
-// lds: the wavefront's LDS region (at least x_lds_bytes<R>(QMAX) bytes).
-template <typename R, int MODE, int FLAGS, int QMAX>
+// Q range [QLO, QHI]: the points-per-lane of the x lines a kernel serves; only
+// the solver variants in that range are compiled into it (their registers would
+// be allocated even when not taken).  SMAX: the most scan steps of any of its
+// lines (3 or 6).
+// lds: the wavefront's LDS region (at least x_lds_bytes<R>(QHI) bytes).
+template <typename R, int MODE, int FLAGS, int Q, int QLO, int QHI, int SMAX>
+__device__ __forceinline__ bool x_item_q(const SweepParams &P, const BatchItem &it, typename CT<R>::V *xl)
+{
+    using V = typename CT<R>::V;
+    if constexpr (QLO <= Q && Q <= QHI) {
+        if (P.xq == Q) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            x_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, (const V *)P.psi, (V *)P.out, (const V *)P.tab, nullptr, it.first,
+                                                 it.count, a, b, c, xl);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename R, int MODE, int FLAGS, int QLO, int QHI, int SMAX>
 __device__ __forceinline__ void run_x_item(const SweepParams &P0, const BatchItem &it, int64_t step, char *lds)
 {
     using V = typename CT<R>::V;
     SweepParams P = P0;
     P.norm_total = P0.norm_total + ((step - 1) & 1);
-    double a = 0.0, b = 0.0, c = 0.0;
-    const V *src = (const V *)P.psi;
-    V *dst = (V *)P.out;
-    const V *tab = (const V *)P.tab;
     V *xl = (V *)lds;
-    if (P.xq == 1) x_scan_wave<R, MODE, FLAGS, 1>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
-    else if (P.xq == 2) x_scan_wave<R, MODE, FLAGS, 2>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
-    else if constexpr (QMAX >= 4) {
-        if (P.xq == 4) x_scan_wave<R, MODE, FLAGS, 4>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
-        else if constexpr (QMAX >= 8) {
-            if (P.xq == 8) x_scan_wave<R, MODE, FLAGS, 8>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
-            else if constexpr (QMAX >= 16) {
-                if (P.xq == 16)
-                    x_scan_wave<R, MODE, FLAGS, 16>(P, src, dst, tab, nullptr, it.first, it.count, a, b, c, xl);
-            }
-        }
-    }
+    x_item_q<R, MODE, FLAGS, 1, QLO, QHI, SMAX>(P, it, xl) || x_item_q<R, MODE, FLAGS, 2, QLO, QHI, SMAX>(P, it, xl) ||
+        x_item_q<R, MODE, FLAGS, 4, QLO, QHI, SMAX>(P, it, xl) || x_item_q<R, MODE, FLAGS, 8, QLO, QHI, SMAX>(P, it, xl) ||
+        x_item_q<R, MODE, FLAGS, 16, QLO, QHI, SMAX>(P, it, xl);
 }
 
-template <typename R, int MODE, int FLAGS>
+// [QLO, QHI]: the points-per-lane of the scan-solved y lines a kernel serves
+// (QHI = 0: windowed items only); SMAX as for x.
+template <typename R, int MODE, int FLAGS, int Q, int QLO, int QHI, int SMAX>
+__device__ __forceinline__ bool y_item_q(const SweepParams &P, const BatchItem &it, double &nacc,
+                                         typename CT<R>::V *t)
+{
+    using V = typename CT<R>::V;
+    if constexpr (QLO <= Q && Q <= QHI) {
+        if (P.xq == Q) {
+            col_tile_wave<R, MODE, FLAGS, Q, SMAX>(P, (const V *)P.psi, (V *)P.out, (const V *)P.tab, it.first,
+                                                   it.count, nacc, t);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename R, int MODE, int FLAGS, int QLO, int QHI, int SMAX>
 __device__ __forceinline__ void run_y_item(const SweepParams &P0, const BatchItem &it, int64_t step, char *lds)
 {
     using V = typename CT<R>::V;
@@ -125,6 +150,22 @@ __device__ __forceinline__ void run_y_item(const SweepParams &P0, const BatchIte
     const V *src = (const V *)P.psi;
     V *dst = (V *)P.out;
     const V *tab = (const V *)P.tab;
+    if constexpr (QHI > 0) {
+        if (it.segs == 0) {  // scan solver on tiles of lines, one partial per item
+            double nacc = 0.0;
+            V *t = (V *)lds;
+            y_item_q<R, MODE, FLAGS, 1, QLO, QHI, SMAX>(P, it, nacc, t) ||
+                y_item_q<R, MODE, FLAGS, 2, QLO, QHI, SMAX>(P, it, nacc, t) ||
+                y_item_q<R, MODE, FLAGS, 4, QLO, QHI, SMAX>(P, it, nacc, t) ||
+                y_item_q<R, MODE, FLAGS, 8, QLO, QHI, SMAX>(P, it, nacc, t);
+            if (FLAGS & F_NORM_OUT) {
+                nacc = wave_sum(nacc);
+                if ((threadIdx.x & (kLanes - 1)) == 0) P.norm_out[it.seg] = nacc;
+            }
+            return;
+        }
+    }
+    if constexpr (QLO > 0) return;  // a scan-only kernel: no windowed items
     const int64_t ngroups = (P.nlines + kLanes - 1) / kLanes;
     const int64_t part = it.first + ngroups * it.seg;
     switch (P.D) {
@@ -142,23 +183,27 @@ __device__ __forceinline__ void run_y_item(const SweepParams &P0, const BatchIte
 
 // ------------------------------------------------------------ phased kernels
 
-template <typename R, int MODE, int QMAX>
-__global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_x(const SweepParams *__restrict__ px,
+// complex64 lines of up to 8 points per lane and at most 3 scan steps: at least
+// three wavefronts per SIMD.  The line solves are latency-bound chains that two
+// would leave the SIMD idle most of the time, and there the register cap costs
+// no spills (elsewhere it would).
+template <typename R, int MODE, int QLO, int QHI, int SMAX>
+__global__ __launch_bounds__(kLanes *kBatchWaves, (sizeof(R) == 4 && QHI <= 8 && SMAX <= 3) ? 3 : 1) void k_batch_x(const SweepParams *__restrict__ px,
                                                                   const BatchItem *__restrict__ items, int64_t nitems,
                                                                   int64_t step, int renorm)
 {
-    __shared__ typename CT<R>::V xl[kBatchWaves][kLanes * (QMAX + 1)];
+    __shared__ typename CT<R>::V xl[kBatchWaves][kLanes * (QHI + 1)];
     const int w = wave_first_lane_i(threadIdx.x / kLanes);
     const int64_t i = (int64_t)blockIdx.x * kBatchWaves + w;
     if (i >= nitems) return;  // whole wavefront
     const BatchItem it = items[i];
     if (MODE == GP_IMAG && renorm)
-        run_x_item<R, MODE, F_FUSE_N | F_RENORM, QMAX>(px[it.prob], it, step, (char *)xl[w]);
+        run_x_item<R, MODE, F_FUSE_N | F_RENORM, QLO, QHI, SMAX>(px[it.prob], it, step, (char *)xl[w]);
     else
-        run_x_item<R, MODE, F_FUSE_N, QMAX>(px[it.prob], it, step, (char *)xl[w]);
+        run_x_item<R, MODE, F_FUSE_N, QLO, QHI, SMAX>(px[it.prob], it, step, (char *)xl[w]);
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int QLO, int QHI, int SMAX>
 __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_y(const SweepParams *__restrict__ py,
                                                                   const BatchItem *__restrict__ items, int64_t nitems,
                                                                   int64_t step, size_t lds_wave)
@@ -168,7 +213,8 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_y(const SweepPara
     const int64_t i = (int64_t)blockIdx.x * kBatchWaves + w;
     if (i >= nitems) return;
     const BatchItem it = items[i];
-    run_y_item<R, MODE, MODE == GP_IMAG ? F_NORM_OUT : 0>(py[it.prob], it, step, lds_raw + (size_t)w * lds_wave);
+    run_y_item<R, MODE, MODE == GP_IMAG ? F_NORM_OUT : 0, QLO, QHI, SMAX>(py[it.prob], it, step,
+                                                                        lds_raw + (size_t)w * lds_wave);
 }
 
 // Per problem: sum of its y partials of `step` (fixed order) into its norm total.
@@ -240,7 +286,7 @@ __device__ __forceinline__ bool wait_at_least(int *ctr, int target, int *error, 
     return ok != 0;
 }
 
-template <typename R, int QMAX>
+template <typename R, int QMAX, int QY, int SMAX>
 __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
     const SweepParams *__restrict__ px, const SweepParams *__restrict__ py, const BatchItem *__restrict__ xi,
     int64_t nxi, const BatchItem *__restrict__ yi, int64_t nyi, const int *__restrict__ nx_per,
@@ -267,7 +313,7 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
             int *ydone = xdone + 1;
             // the previous step's y items of this problem are done
             if (!wait_at_least(ydone + 2 * it.prob, (int)(sl * ny_per[it.prob]), error, limit)) break;
-            run_x_item<R, GP_REAL, F_FUSE_N, QMAX>(px[it.prob], it, step0 + sl, lds);
+            run_x_item<R, GP_REAL, F_FUSE_N, 1, QMAX, SMAX>(px[it.prob], it, step0 + sl, lds);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if ((threadIdx.x & (kLanes - 1)) == 0)
                 __hip_atomic_fetch_add(xdone + 2 * it.prob, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -275,7 +321,7 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
             const BatchItem it = yi[r - nxi];
             // this step's x items of this problem are done
             if (!wait_at_least(xdone + 2 * it.prob, (int)((sl + 1) * nx_per[it.prob]), error, limit)) break;
-            run_y_item<R, GP_REAL, 0>(py[it.prob], it, step0 + sl, lds);
+            run_y_item<R, GP_REAL, 0, 0, QY, SMAX>(py[it.prob], it, step0 + sl, lds);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if ((threadIdx.x & (kLanes - 1)) == 0)
                 __hip_atomic_fetch_add(xdone + 2 * it.prob + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -312,8 +358,7 @@ static gp_status upload(void **dst, const void *src, size_t bytes)
     return GP_OK;
 }
 
-// y segments of problem k: at most the plan's count, each segment at least
-// four windows long.
+// y segments of problem k (windowed y lines): at most the plan's count.
 static int y_segments(const gp_plan *p, int want)
 {
     const AxisPlan &A = p->ax[1];
@@ -330,10 +375,17 @@ static gp_status prepare(gp_batch *b, void *const *psis)
     if (same) return GP_OK;
     free_batch_device(b);
     std::vector<SweepParams> px(b->count), py(b->count);
-    std::vector<BatchItem> xi, yi;
+    std::vector<std::vector<BatchItem>> xk(b->count), yk(b->count);  // per problem
     std::vector<int> nx_per(b->count), ny_per(b->count);
     std::vector<int64_t> nparts(b->count);
     size_t lds_wave = 0;
+    auto lds_x = [&](int q) { return b->prec == GP_C128 ? x_lds_bytes<double>(q) : x_lds_bytes<float>(q); };
+    auto lds_tile = [&](int q) {
+        return b->prec == GP_C128 ? col_tile_lds_bytes<double>(q) : col_tile_lds_bytes<float>(q);
+    };
+    auto lds_ring = [&](int L) {
+        return b->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(L) : window_lds_bytes<float, kStrided, 4>(L);
+    };
     for (int k = 0; k < b->count; ++k) {
         gp_plan *p = b->plans[k];
         // 2D: x psi -> work, y work -> psi
@@ -343,27 +395,38 @@ static gp_status prepare(gp_batch *b, void *const *psis)
         py[k].norm_total = norm_total(p, 0);
         py[k].norm_out = norm_partials(p, 0);
         const int64_t ny = p->n[1], nx = p->n[0];
-        int cnt = 0;
-        for (int64_t l = 0; l < ny; l += b->cfg.lines) {
-            xi.push_back({k, 0, 1, (int)std::min<int64_t>(b->cfg.lines, ny - l), l});
-            ++cnt;
-        }
-        nx_per[k] = cnt;
-        const int segs = y_segments(p, b->cfg.ysegs);
-        const int64_t groups = (nx + kLanes - 1) / kLanes;
-        cnt = 0;
-        for (int s = 0; s < segs; ++s)
-            for (int64_t g = 0; g < groups; ++g) {
-                yi.push_back({k, s, segs, 0, g});
-                ++cnt;
+        for (int64_t l = 0; l < ny; l += b->cfg.lines)
+            xk[k].push_back({k, 0, 1, (int)std::min<int64_t>(b->cfg.lines, ny - l), l});
+        nx_per[k] = (int)xk[k].size();
+        if (p->ax[1].xq > 0) {  // scan-solved y lines: items of whole tiles, one norm partial each
+            const int64_t tl = b->prec == GP_C128 ? col_tile_lines<double>() : col_tile_lines<float>();
+            int64_t per = std::max<int64_t>(b->cfg.lines, (nx + p->n_norm - 1) / p->n_norm);
+            per = (per + tl - 1) / tl * tl;
+            for (int64_t l = 0; l < nx; l += per) {
+                const int slot = (int)yk[k].size();
+                yk[k].push_back({k, slot, 0, (int)std::min<int64_t>(per, nx - l), l});
             }
-        ny_per[k] = cnt;
-        nparts[k] = groups * segs;
-        lds_wave = std::max(lds_wave, b->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(p->ax[1].L)
-                                                         : window_lds_bytes<float, kStrided, 4>(p->ax[1].L));
+            nparts[k] = (int64_t)yk[k].size();
+            lds_wave = std::max(lds_wave, lds_tile(p->ax[1].xq));
+        } else {
+            const int segs = y_segments(p, b->cfg.ysegs);
+            const int64_t groups = (nx + kLanes - 1) / kLanes;
+            for (int s = 0; s < segs; ++s)
+                for (int64_t g = 0; g < groups; ++g) yk[k].push_back({k, s, segs, 0, g});
+            nparts[k] = groups * segs;
+            lds_wave = std::max(lds_wave, lds_ring(p->ax[1].L));
+        }
+        ny_per[k] = (int)yk[k].size();
         // the persistent kernel's x items use the same region for their transposes
-        lds_wave = std::max(lds_wave, b->prec == GP_C128 ? x_lds_bytes<double>(p->ax[0].xq)
-                                                         : x_lds_bytes<float>(p->ax[0].xq));
+        lds_wave = std::max(lds_wave, lds_x(p->ax[0].xq));
+    }
+    std::vector<BatchItem> xi, yi;
+    b->smax = 3;
+    for (int k = 0; k < b->count; ++k) {
+        xi.insert(xi.end(), xk[k].begin(), xk[k].end());
+        yi.insert(yi.end(), yk[k].begin(), yk[k].end());
+        const gp_plan *p = b->plans[k];
+        if (p->ax[0].scan_steps > 3 || (p->ax[1].xq > 0 && p->ax[1].scan_steps > 3)) b->smax = 6;
     }
     gp_status st = upload((void **)&b->d_px, px.data(), px.size() * sizeof(SweepParams));
     if (st == GP_OK) st = upload((void **)&b->d_py, py.data(), py.size() * sizeof(SweepParams));
@@ -386,17 +449,17 @@ static gp_status prepare(gp_batch *b, void *const *psis)
     return GP_OK;
 }
 
-template <typename R, int MODE, int QMAX>
+template <typename R, int MODE, int QMAX, int QY, int SMAX>
 static hipError_t run_phased(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
 {
     const unsigned gx = (unsigned)((b->nxi + kBatchWaves - 1) / kBatchWaves);
     const unsigned gy = (unsigned)((b->nyi + kBatchWaves - 1) / kBatchWaves);
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n = step0 + k;
-        hipLaunchKernelGGL((k_batch_x<R, MODE, QMAX>), dim3(gx), dim3(kLanes * kBatchWaves), 0, s, b->d_px, b->d_xi, b->nxi,
-                           n, (int)(k > 0));
-        hipLaunchKernelGGL((k_batch_y<R, MODE>), dim3(gy), dim3(kLanes * kBatchWaves), kBatchWaves * b->lds_wave, s,
-                           b->d_py, b->d_yi, b->nyi, n, b->lds_wave);
+        hipLaunchKernelGGL((k_batch_x<R, MODE, 1, QMAX, SMAX>), dim3(gx), dim3(kLanes * kBatchWaves), 0, s, b->d_px,
+                           b->d_xi, b->nxi, n, (int)(k > 0));
+        hipLaunchKernelGGL((k_batch_y<R, MODE, 0, QY, SMAX>), dim3(gy), dim3(kLanes * kBatchWaves),
+                           kBatchWaves * b->lds_wave, s, b->d_py, b->d_yi, b->nyi, n, b->lds_wave);
         if (MODE == GP_IMAG)
             hipLaunchKernelGGL(k_batch_norm_final, dim3(b->count), dim3(256), 0, s, b->d_py, b->d_nparts, n);
         hipError_t e = hipGetLastError();
@@ -407,7 +470,7 @@ static hipError_t run_phased(gp_batch *b, int64_t step0, int64_t nsteps, hipStre
     return hipGetLastError();
 }
 
-template <typename R, int QMAX>
+template <typename R, int QMAX, int QY, int SMAX>
 static hipError_t run_persistent(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
 {
     // the queue head and the per-problem counters are 32-bit: launches of at most 2^30 items
@@ -417,7 +480,7 @@ static hipError_t run_persistent(gp_batch *b, int64_t step0, int64_t nsteps, hip
     for (int64_t k0 = 0; k0 < nsteps; k0 += chunk) {
         const int64_t m = std::min(chunk, nsteps - k0);
         hipLaunchKernelGGL(k_fill_zero_i32, dim3(1), dim3(256), 0, s, b->d_ctr, nctr);
-        hipLaunchKernelGGL((k_batch_persistent<R, QMAX>), dim3((unsigned)b->cfg.grid), dim3(kLanes * kBatchWaves),
+        hipLaunchKernelGGL((k_batch_persistent<R, QMAX, QY, SMAX>), dim3((unsigned)b->cfg.grid), dim3(kLanes * kBatchWaves),
                            kBatchWaves * b->lds_wave, s, b->d_px, b->d_py, b->d_xi, b->nxi, b->d_yi, b->nyi,
                            b->d_nx_per, b->d_ny_per, step0 + k0, m, b->d_ctr, b->lds_wave, b->cfg.spin_limit);
         hipError_t e = hipGetLastError();
@@ -426,12 +489,28 @@ static hipError_t run_persistent(gp_batch *b, int64_t step0, int64_t nsteps, hip
     return hipSuccess;
 }
 
+template <typename R, int QMAX, int QY, int SMAX>
+static hipError_t run_batch_s(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    if (b->cfg.persistent && b->mode == GP_REAL) return run_persistent<R, QMAX, QY, SMAX>(b, step0, nsteps, s);
+    return b->mode == GP_IMAG ? run_phased<R, GP_IMAG, QMAX, QY, SMAX>(b, step0, nsteps, s)
+                              : run_phased<R, GP_REAL, QMAX, QY, SMAX>(b, step0, nsteps, s);
+}
+
+template <typename R, int QMAX, int QY>
+static hipError_t run_batch_qy(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
+{
+    return b->smax <= 3 ? run_batch_s<R, QMAX, QY, 3>(b, step0, nsteps, s)
+                        : run_batch_s<R, QMAX, QY, 6>(b, step0, nsteps, s);
+}
+
 template <typename R, int QMAX>
 static hipError_t run_batch_q(gp_batch *b, int64_t step0, int64_t nsteps, hipStream_t s)
 {
-    if (b->cfg.persistent && b->mode == GP_REAL) return run_persistent<R, QMAX>(b, step0, nsteps, s);
-    return b->mode == GP_IMAG ? run_phased<R, GP_IMAG, QMAX>(b, step0, nsteps, s)
-                              : run_phased<R, GP_REAL, QMAX>(b, step0, nsteps, s);
+    if (b->qmax_y == 0) return run_batch_qy<R, QMAX, 0>(b, step0, nsteps, s);
+    if (b->qmax_y <= 2) return run_batch_qy<R, QMAX, 2>(b, step0, nsteps, s);
+    if (b->qmax_y <= 4) return run_batch_qy<R, QMAX, 4>(b, step0, nsteps, s);
+    return run_batch_qy<R, QMAX, 8>(b, step0, nsteps, s);
 }
 
 template <typename R>
@@ -462,14 +541,16 @@ static gp_status check_error_flag(gp_batch *b, hipStream_t s)
     return GP_OK;
 }
 
-// The batched kernels run the x sweep with the scan solver and the y sweep with
-// the windowed solver of depth 1..8 blocks of 4 points, four wavefronts per
-// workgroup each holding its ring (or x transpose buffer) in LDS.  A problem
-// outside that (an exact two-pass y solve, a deeper window, a ring set too
-// large for the device's LDS) is rejected when the batch is created.
-// The y-sweep half of the check runs on the host before any HIP call.
+// The batched kernels run the x sweep with the scan solver and the y sweep
+// with the scan solver (y lines up to 512 points, exact) or the windowed solver
+// of depth 1..8 blocks of 4 points, four wavefronts per workgroup each holding
+// its ring (or x transpose buffer) in LDS.  A problem outside that (a longer y
+// line that would need the exact two-pass solve or a deeper window, a ring set
+// too large for the device's LDS) is rejected when the batch is created.  The
+// y-sweep half of the check runs on the host before any HIP call.
 static gp_status batch_y_supported(const AxisPlan &Y)
 {
+    if (Y.n <= (int64_t)kColMaxQ * kLanes) return GP_OK;  // scan solver
     if (Y.K < 0 || Y.B != 4 || Y.D < 1 || Y.D > 8)
         return set_error("batched y sweep needs a windowed solve of 1..8 blocks (dt/dx^2 too large)"),
                GP_EUNSUPPORTED;
@@ -482,8 +563,10 @@ static gp_status batch_supports(const gp_plan *p, int max_lds)
     if (X.xq < 1 || X.xq > kXMaxQ) return set_error("batched x sweep needs 1 <= nx <= 1024"), GP_EUNSUPPORTED;
     const gp_status st = batch_y_supported(Y);
     if (st != GP_OK) return st;
-    const size_t ring = p->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(Y.L)
-                                           : window_lds_bytes<float, kStrided, 4>(Y.L);
+    const size_t ring = Y.xq > 0 ? (p->prec == GP_C128 ? col_tile_lds_bytes<double>(Y.xq)
+                                                       : col_tile_lds_bytes<float>(Y.xq))
+                        : p->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(Y.L)
+                                             : window_lds_bytes<float, kStrided, 4>(Y.L);
     const size_t xl = p->prec == GP_C128 ? x_lds_bytes<double>(X.xq) : x_lds_bytes<float>(X.xq);
     if (max_lds > 0 && (int64_t)kBatchWaves * (int64_t)std::max(ring, xl) > (int64_t)max_lds)
         return set_error("batched sweep's LDS (4 wavefronts' rings) exceeds the device limit"), GP_EUNSUPPORTED;
@@ -551,6 +634,7 @@ gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n, const dou
         }
         b->plans.push_back(p);
         b->qmax = std::max(b->qmax, p->ax[0].xq);
+        b->qmax_y = std::max(b->qmax_y, p->ax[1].xq);
         st = batch_supports(p, max_lds);
         if (st != GP_OK) {
             gp_batch_destroy(b);

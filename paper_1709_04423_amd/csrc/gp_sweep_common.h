@@ -247,7 +247,7 @@ __device__ __forceinline__ cp<R> potential_substep(cp<R> u, int64_t q, const Swe
 // interleave; values whose angle exceeds the series range (rare; the wavefront
 // checks once) are redone with the library functions.
 template <typename R, int MODE, int FLAGS, int Q>
-__device__ __forceinline__ void potential_substep_q(cp<R> (&u)[Q], int q0, int qs, const SweepParams &P,
+__device__ __forceinline__ void potential_substep_n(cp<R> *u, int q0, int qs, const SweepParams &P,
                                                     const LineCtx<R> &L)
 {
     R th[Q];
@@ -302,6 +302,17 @@ __device__ __forceinline__ void potential_substep_q(cp<R> (&u)[Q], int q0, int q
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) u[i] = {u[i].re * f[i], u[i].im * f[i]};
+}
+
+// In groups of at most four values: enough independent chains to fill the
+// pipeline without holding every value's angle, sine and cosine at once.
+template <typename R, int MODE, int FLAGS, int Q>
+__device__ __forceinline__ void potential_substep_q(cp<R> (&u)[Q], int q0, int qs, const SweepParams &P,
+                                                    const LineCtx<R> &L)
+{
+    constexpr int G = Q < 4 ? Q : 4;
+#pragma unroll
+    for (int i = 0; i < Q; i += G) potential_substep_n<R, MODE, FLAGS, G>(u + i, q0 + qs * i, qs, P, L);
 }
 
 // Adjoint of the potential substep at point t: lam (gradient of its output)

@@ -360,4 +360,79 @@ __device__ __forceinline__ void col_scan_wave(const SweepParams &P, const typena
     }
 }
 
+// Strided lines in tiles: one wavefront loads a tile of T neighbouring lines
+// (T values = 32 bytes of each row, so four such tiles fill a 128-byte cache
+// line) with every load instruction covering 64/T rows, keeps it in LDS in the
+// solver's padded layout, solves the tile's lines one after another from LDS
+// and stores the tile back the same way.  Against one line per load pass this
+// reads each row segment once per tile instead of once per line.  Lines first ..
+// first + count - 1 (those below P.nlines), T at a time; lds: this wavefront's
+// col_tile_lds_bytes<R>(Q) bytes.  F_NORM_OUT sums |u'|^2 into nacc.
+template <typename R> __host__ __device__ constexpr int col_tile_lines() { return 32 / (int)sizeof(typename CT<R>::V); }
+template <typename R> __host__ __device__ constexpr size_t col_tile_lds_bytes(int Q)
+{
+    return (size_t)col_tile_lines<R>() * kLanes * (Q + 1) * sizeof(typename CT<R>::V);
+}
+
+template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
+__device__ __forceinline__ void col_tile_wave(const SweepParams &P, const typename CT<R>::V *src,
+                                              typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
+                                              int64_t first, int count, double &nacc, typename CT<R>::V *lds)
+{
+    using V = typename CT<R>::V;
+    constexpr int T = col_tile_lines<R>();
+    constexpr int RPI = kLanes / T;         // rows per load instruction
+    constexpr int NLD = kLanes * Q / RPI;   // load instructions per tile (rows 0 .. 64 Q - 1)
+    constexpr int LSTR = kLanes * (Q + 1);  // LDS values per line
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int lc = lane % T, lr = lane / T;
+    const int64_t n = P.n;
+    const cp<R> zero = {R(0), R(0)};
+    XConsts<R, Q, SMAX> K;
+    x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+#pragma unroll 1
+    for (int c0 = 0; c0 < count; c0 += T) {
+        const int64_t line = first + c0 + lc;
+        const bool mine = c0 + lc < count && line < P.nlines;  // this lane's line of the tile exists
+        const int64_t lcl = line < P.nlines ? line : P.nlines - 1;
+        const int64_t base = (lcl % P.m1) * P.s1 + (lcl / P.m1) * P.s2;
+        V *col = lds + lc * LSTR;
+        // eight loads in flight per lane: enough to cover the latency, while a
+        // full unroll would hold the whole tile in registers next to the
+        // solver's constants
+#pragma unroll 8
+        for (int k = 0; k < NLD; ++k) {  // rows past the line's end are zeros
+            const int r = lr + RPI * k;
+            const V v = src[base + (r < n ? r : n - 1) * P.stride];
+            col[r + r / Q] = r < n ? v : to_v<V>(zero);
+        }
+        wave_lds_sync();
+        int nt = count - c0 < T ? count - c0 : T;  // lines of this tile
+        if (P.nlines - (first + c0) < nt) nt = (int)(P.nlines - (first + c0));
+#pragma unroll 1
+        for (int c = 0; c < nt; ++c) {
+            V *cl = lds + c * LSTR;
+            cp<R> u[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) u[i] = from_v<R>(cl[lane * (Q + 1) + i]);
+            x_line_solve<R, MODE, Q, SMAX>(P, K, P.scan_steps, lane, u);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                cl[lane * (Q + 1) + i] = to_v<V>(u[i]);
+                if ((FLAGS & F_NORM_OUT) && (int64_t)lane * Q + i < n)
+                    nacc += (double)u[i].re * (double)u[i].re + (double)u[i].im * (double)u[i].im;
+            }
+        }
+        wave_lds_sync();
+        if (mine) {
+#pragma unroll 8
+            for (int k = 0; k < NLD; ++k) {
+                const int r = lr + RPI * k;
+                if (r < n) dst[base + r * P.stride] = col[r + r / Q];
+            }
+        }
+        wave_lds_sync();  // the next tile's loads overwrite these slots
+    }
+}
+
 }  // namespace gp

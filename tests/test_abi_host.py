@@ -135,8 +135,9 @@ def _batch_create(sizes, dx, dt, mode, prec, traps=None):
 def test_batch_create_rejects_problems_the_batched_kernels_do_not_run():
     # dx = 0.05, dt = 5e-3 in complex128 real time: the y recurrence contracts so
     # slowly that its window would exceed 8 blocks (or the exact solver would be
-    # needed); the batch must refuse it up front instead of skipping the y sweep
-    st, h = _batch_create([(64, 64), (128, 96)], 0.05, 5e-3, binding.GP_REAL, binding.GP_C128)
+    # needed) on a y line too long for the scan solver (over 512 points); the
+    # batch must refuse it up front instead of skipping the y sweep
+    st, h = _batch_create([(64, 64), (128, 600)], 0.05, 5e-3, binding.GP_REAL, binding.GP_C128)
     assert st == binding.GP_EUNSUPPORTED and not h.value
     assert b"windowed" in binding.lib().gp_last_error()
     # a per-problem trap schedule is not supported by the batched launch
