@@ -117,15 +117,7 @@ static hipError_t launch_window_d(const AxisPlan &A, const SweepParams &P, const
         case 4: launch_window<R, MODE, FLAGS, ACC, 4, 16>(A, P, tab, s); break;
         default: return hipErrorInvalidValue;
         }
-    } else if (A.B == 8) {  // blocks of 8 points (complex64 strided axes)
-        switch (A.D) {
-        case 1: launch_window<R, MODE, FLAGS, ACC, 1, 8>(A, P, tab, s); break;
-        case 2: launch_window<R, MODE, FLAGS, ACC, 2, 8>(A, P, tab, s); break;
-        case 3: launch_window<R, MODE, FLAGS, ACC, 3, 8>(A, P, tab, s); break;
-        case 4: launch_window<R, MODE, FLAGS, ACC, 4, 8>(A, P, tab, s); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {  // blocks of 4 points (complex128 strided axes)
+    } else {  // blocks of 4 points (strided axes, both precisions)
         if (A.B != 4) return hipErrorInvalidValue;
         switch (A.D) {
         case 1: launch_window<R, MODE, FLAGS, ACC, 1, 4>(A, P, tab, s); break;

@@ -369,9 +369,12 @@ __device__ __forceinline__ void col_scan_wave(const SweepParams &P, const typena
 // first + count - 1 (those below P.nlines), T at a time; lds: this wavefront's
 // col_tile_lds_bytes<R>(Q) bytes.  F_NORM_OUT sums |u'|^2 into nacc.
 template <typename R> __host__ __device__ constexpr int col_tile_lines() { return 32 / (int)sizeof(typename CT<R>::V); }
+// One line's LDS slots: the padded layout plus one value, so that the T lines'
+// slots of a row fall in different banks.
+__host__ __device__ constexpr int col_tile_stride(int Q) { return kLanes * (Q + 1) + 1; }
 template <typename R> __host__ __device__ constexpr size_t col_tile_lds_bytes(int Q)
 {
-    return (size_t)col_tile_lines<R>() * kLanes * (Q + 1) * sizeof(typename CT<R>::V);
+    return (size_t)col_tile_lines<R>() * col_tile_stride(Q) * sizeof(typename CT<R>::V);
 }
 
 template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
@@ -383,7 +386,7 @@ __device__ __forceinline__ void col_tile_wave(const SweepParams &P, const typena
     constexpr int T = col_tile_lines<R>();
     constexpr int RPI = kLanes / T;         // rows per load instruction
     constexpr int NLD = kLanes * Q / RPI;   // load instructions per tile (rows 0 .. 64 Q - 1)
-    constexpr int LSTR = kLanes * (Q + 1);  // LDS values per line
+    constexpr int LSTR = col_tile_stride(Q);  // LDS values per line
     const int lane = threadIdx.x & (kLanes - 1);
     const int lc = lane % T, lr = lane / T;
     const int64_t n = P.n;
@@ -397,14 +400,23 @@ __device__ __forceinline__ void col_tile_wave(const SweepParams &P, const typena
         const int64_t lcl = line < P.nlines ? line : P.nlines - 1;
         const int64_t base = (lcl % P.m1) * P.s1 + (lcl / P.m1) * P.s2;
         V *col = lds + lc * LSTR;
-        // eight loads in flight per lane: enough to cover the latency, while a
-        // full unroll would hold the whole tile in registers next to the
-        // solver's constants
-#pragma unroll 8
-        for (int k = 0; k < NLD; ++k) {  // rows past the line's end are zeros
-            const int r = lr + RPI * k;
-            const V v = src[base + (r < n ? r : n - 1) * P.stride];
-            col[r + r / Q] = r < n ? v : to_v<V>(zero);
+        // loads in groups of 128 bytes per lane (16 complex64 or 8 complex128
+        // values), all in flight together: a full unroll would hold the whole
+        // tile in registers next to the solver's constants
+        constexpr int GRP = NLD < 128 / (int)sizeof(V) ? NLD : 128 / (int)sizeof(V);
+#pragma unroll 1
+        for (int k0 = 0; k0 < NLD; k0 += GRP) {
+            V v[GRP];
+#pragma unroll
+            for (int k = 0; k < GRP; ++k) {  // rows past the line's end are zeros
+                const int r = lr + RPI * (k0 + k);
+                v[k] = src[base + (r < n ? r : n - 1) * P.stride];
+            }
+#pragma unroll
+            for (int k = 0; k < GRP; ++k) {
+                const int r = lr + RPI * (k0 + k);
+                col[r + r / Q] = r < n ? v[k] : to_v<V>(zero);
+            }
         }
         wave_lds_sync();
         int nt = count - c0 < T ? count - c0 : T;  // lines of this tile
