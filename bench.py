@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--out", help="summary file written by the --summarize-* modes")
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="", help="the command that produced the profile (recorded)")
-    ap.add_argument("--traffic-kernel", default="k_sweep_xy<double",
+    ap.add_argument("--traffic-kernel", default="k_sweep_xy_reg<double",
                     help="kernel-name prefix whose bytes per launch the traffic summary records")
     ap.add_argument("--step-kernels", default="",
                     help="semicolon-separated kernel-name prefixes (optionally @grid-size) launched once per step: the traffic summary "

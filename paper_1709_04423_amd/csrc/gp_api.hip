@@ -382,6 +382,7 @@ static void free_plan(gp_plan *p)
     if (p->d_work) hipFree(p->d_work);
     if (p->d_norm) hipFree(p->d_norm);
     if (p->d_adj) hipFree(p->d_adj);
+    if (p->d_adj_done) hipFree(p->d_adj_done);
     if (p->d_obs) hipFree(p->d_obs);
     for (hipEvent_t e : p->timing.ev) hipEventDestroy(e);
     delete p;
@@ -601,6 +602,13 @@ static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n
     if (st == GP_OK && ndim >= 2) st = alloc(&p->d_work, (size_t)npts * elem_bytes(prec), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_norm, (2 * maxg + 2) * sizeof(double), p->device_bytes);
     if (st == GP_OK) st = alloc((void **)&p->d_adj, 2 * maxg * sizeof(double), p->device_bytes);
+    if (st == GP_OK && mode == GP_REAL) {
+        st = alloc((void **)&p->d_adj_done, sizeof(int), p->device_bytes);
+        if (st == GP_OK && hipMemset(p->d_adj_done, 0, sizeof(int)) != hipSuccess) {
+            set_error("hipMemset(adjoint counter)");
+            st = GP_EHIP;
+        }
+    }
     if (st == GP_OK)
         st = alloc((void **)&p->d_obs, (p->n_obs_blocks + 1) * kObsFields * sizeof(double), p->device_bytes);
     if (st != GP_OK) {
@@ -742,6 +750,49 @@ gp_status gp_thomas_table(int64_t n, double dx, double dt, gp_mode mode, gp_prec
     return GP_OK;
 }
 
+// nsteps Cartesian steps from step index p->step (the index is not advanced).
+// states != null (real time): the state before step k is written to
+// states + k * grid bytes, by the x scan kernel as it loads (otherwise a copy).
+static gp_status cartesian_steps(gp_plan *p, void *psi, int64_t nsteps, void *states, hipStream_t s)
+{
+    const bool imag = p->mode == GP_IMAG;
+    const bool fused = p->ndim == 3 && p->xy_segs > 0 && p->xy_enabled;
+    const size_t bytes = (size_t)p->npts * elem_bytes(p->prec);
+    hipError_t e;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const int64_t n = p->step + k;
+        void *copy_to = states ? (char *)states + (size_t)k * bytes : nullptr;
+        const bool copy_in_x = copy_to && !fused && p->ax[0].xq > 0;
+        if (copy_to && !copy_in_x) {
+            e = launch_copy(copy_to, psi, (int64_t)bytes, s);
+            if (e != hipSuccess) return hip_fail(e, "state copy launch");
+        }
+        if (fused) {  // x and y in one pass psi -> work, then z work -> psi
+            e = launch_xy(p, psi, p->d_work, F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0), n, s);
+            if (e != hipSuccess) return hip_fail(e, "fused x+y sweep launch");
+        }
+        for (int a = fused ? 2 : 0; a < p->ndim; ++a) {
+            int flags = 0;
+            if (a == 0) flags |= F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
+            if (imag && a == p->ndim - 1) flags |= F_NORM_OUT;
+            SweepExtras x;
+            if (a == 0 && copy_in_x) {
+                flags |= F_COPY_IN;
+                x.copy_out = copy_to;
+            }
+            void *src, *dst;
+            sweep_buffers(p, psi, a, false, &src, &dst);
+            e = launch_sweep(p, a, src, dst, flags, false, n, nullptr, s, &x);
+            if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        }
+        if (imag) {
+            e = launch_norm_final(p, n, s);
+            if (e != hipSuccess) return hip_fail(e, "norm launch");
+        }
+    }
+    return GP_OK;
+}
+
 gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
 {
     if (!p || !psi || nsteps < 0) return set_error("bad plan, psi or nsteps"), GP_EINVAL;
@@ -771,27 +822,8 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
         }
         return GP_OK;
     }
-    const bool fused = p->ndim == 3 && p->xy_segs > 0 && p->xy_enabled;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        const int64_t n = p->step + k;
-        if (fused) {  // x and y in one pass psi -> work, then z work -> psi
-            e = launch_xy(p, psi, p->d_work, F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0), n, s);
-            if (e != hipSuccess) return hip_fail(e, "fused x+y sweep launch");
-        }
-        for (int a = fused ? 2 : 0; a < p->ndim; ++a) {
-            int flags = 0;
-            if (a == 0) flags |= F_FUSE_N | ((imag && k > 0) ? F_RENORM : 0);
-            if (imag && a == p->ndim - 1) flags |= F_NORM_OUT;
-            void *src, *dst;
-            sweep_buffers(p, psi, a, false, &src, &dst);
-            e = launch_sweep(p, a, src, dst, flags, false, n, nullptr, s);
-            if (e != hipSuccess) return hip_fail(e, "sweep launch");
-        }
-        if (imag) {
-            e = launch_norm_final(p, n, s);
-            if (e != hipSuccess) return hip_fail(e, "norm launch");
-        }
-    }
+    const gp_status st = cartesian_steps(p, psi, nsteps, nullptr, s);
+    if (st != GP_OK) return st;
     p->step += nsteps;
     if (imag) {
         e = launch_scale(p, psi, s);
@@ -850,13 +882,9 @@ gp_status gp_step_record(gp_plan *p, void *psi, int64_t nsteps, void *states, vo
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    const size_t bytes = (size_t)p->npts * elem_bytes(p->prec);
-    for (int64_t k = 0; k < nsteps; ++k) {
-        e = launch_copy((char *)states + (size_t)k * bytes, psi, (int64_t)bytes, s);
-        if (e != hipSuccess) return hip_fail(e, "state copy launch");
-        const gp_status st = gp_step(p, psi, 1, stream);
-        if (st != GP_OK) return st;
-    }
+    const gp_status st = cartesian_steps(p, psi, nsteps, states, s);
+    if (st != GP_OK) return st;
+    p->step += nsteps;
     return GP_OK;
 }
 
@@ -874,17 +902,28 @@ gp_status gp_step_adjoint(gp_plan *p, const void *states, void *lambda, int64_t 
     for (int64_t k = nsteps - 1; k >= 0; --k) {
         const int64_t n = n_first + k;
         const void *st = (const char *)states + (size_t)k * bytes;
-        for (int a = p->ndim - 1; a >= 0; --a) {
-            void *src, *dst;
-            sweep_buffers(p, lambda, a, true, &src, &dst);
-            e = launch_sweep(p, a, src, dst, a == 0 ? F_ADJ_N : 0, true, n, st, s);
-            if (e != hipSuccess) return hip_fail(e, "adjoint sweep launch");
-        }
         double w[3];
         omega_at_step(p, n, w);
         const double coeff = p->dt * w[p->sched_axis];
-        e = launch_adj_reduce(p, nparts, coeff, dsched ? dsched + k : nullptr, dg, s);
-        if (e != hipSuccess) return hip_fail(e, "adjoint reduce launch");
+        // the x scan kernel reduces the gradient sums itself (its last workgroup)
+        const bool fold = p->ax[0].xq > 0 && p->d_adj_done;
+        SweepExtras x;
+        if (fold) {
+            x.adj_done = p->d_adj_done;
+            x.adj_dsched = dsched ? dsched + k : nullptr;
+            x.adj_dg = dg;
+            x.adj_coeff = coeff;
+        }
+        for (int a = p->ndim - 1; a >= 0; --a) {
+            void *src, *dst;
+            sweep_buffers(p, lambda, a, true, &src, &dst);
+            e = launch_sweep(p, a, src, dst, a == 0 ? F_ADJ_N : 0, true, n, st, s, a == 0 ? &x : nullptr);
+            if (e != hipSuccess) return hip_fail(e, "adjoint sweep launch");
+        }
+        if (!fold) {
+            e = launch_adj_reduce(p, nparts, coeff, dsched ? dsched + k : nullptr, dg, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint reduce launch");
+        }
     }
     return GP_OK;
 }

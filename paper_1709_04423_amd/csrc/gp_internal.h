@@ -36,6 +36,7 @@ enum SweepFlags {
     F_RENORM = 2,   // scale loaded values by 1/sqrt(dV * sum of norm partials) first
     F_NORM_OUT = 4, // write an FP64 per-workgroup partial of sum |u'|^2
     F_ADJ_N = 8,    // adjoint of the potential substep applied at store (axis 0)
+    F_COPY_IN = 16, // also write every loaded input value to copy_out (axis 0 scan kernel)
 };
 
 constexpr int kLanes = 64;      // one wavefront = one workgroup of the sweeps
@@ -77,6 +78,13 @@ struct SweepParams {
     double *norm_out;     // F_NORM_OUT partials, one per workgroup
     int64_t n_norm;       // partial slots per step parity (batched kernels offset by parity)
     double *adj_out;      // F_ADJ_N partials, two per workgroup
+    // F_ADJ_N in the x scan kernel: the last workgroup to finish sums the
+    // partials (adj_done counts finished workgroups and is reset by that one)
+    // into *adj_dsched = adj_coeff sum_w and *adj_dg += dt sum_g
+    int *adj_done;
+    double *adj_dsched, *adj_dg;
+    double adj_coeff;
+    void *copy_out;       // F_COPY_IN: where the input values are copied
     int radial_d;         // symmetric traps: dimension of the radial axis 0 (2 or 3; 0 Cartesian)
 };
 
@@ -137,6 +145,7 @@ struct gp_plan {
     double *d_norm = nullptr;       // norm partials of the last sweep
     int64_t n_norm = 0;
     double *d_adj = nullptr;        // adjoint partials (2 per workgroup)
+    int *d_adj_done = nullptr;      // finished-workgroup counter of the x adjoint sweep (zero between launches)
     int64_t n_adj = 0;
     double *d_obs = nullptr;        // observable partials + final sums
     int64_t n_obs_blocks = 0;
@@ -160,9 +169,18 @@ void timing_end(gp_plan *p, hipStream_t s);
 size_t elem_bytes(gp_prec prec);
 double coord0(int64_t n);  // x0 such that x_i = (i + x0) dx
 
+// Extras of a sweep launch beyond its grids (null: not used): the x scan
+// kernel's folded adjoint reduce (F_ADJ_N) and its input copy (F_COPY_IN).
+struct SweepExtras {
+    int *adj_done = nullptr;
+    double *adj_dsched = nullptr, *adj_dg = nullptr;
+    double adj_coeff = 0.0;
+    void *copy_out = nullptr;
+};
+
 // Sweep along one axis; flags per SweepFlags; adjoint selects the conjugate map.
 hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
-                        int64_t step_index, const void *state, hipStream_t s);
+                        int64_t step_index, const void *state, hipStream_t s, const SweepExtras *extras = nullptr);
 SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void *dst, bool adjoint,
                               int64_t step_index, const void *state);
 // Windowed / two-pass sweep of one axis in one precision (gp_sweep_c128.hip, gp_sweep_c64.hip).

@@ -78,10 +78,17 @@ SweepParams make_sweep_params(const gp_plan *p, int axis, const void *src, void 
 }
 
 hipError_t launch_sweep(gp_plan *p, int axis, const void *src, void *dst, int flags, bool adjoint,
-                        int64_t step_index, const void *state, hipStream_t s)
+                        int64_t step_index, const void *state, hipStream_t s, const SweepExtras *extras)
 {
     const AxisPlan &A = p->ax[axis];
-    const SweepParams P = make_sweep_params(p, axis, src, dst, adjoint, step_index, state);
+    SweepParams P = make_sweep_params(p, axis, src, dst, adjoint, step_index, state);
+    if (extras) {
+        P.adj_done = extras->adj_done;
+        P.adj_dsched = extras->adj_dsched;
+        P.adj_dg = extras->adj_dg;
+        P.adj_coeff = extras->adj_coeff;
+        P.copy_out = extras->copy_out;
+    }
     const bool exact = A.K < 0;
     const bool tr = axis == 0;  // x lines too long for the scan kernel: coalesced through an LDS tile
     const void *tab = P.tab;

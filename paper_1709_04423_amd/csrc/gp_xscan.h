@@ -270,6 +270,11 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
         cp<R> u[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) u[i] = lane + kLanes * i < n ? from_v<R>(nxt[i]) : zero;
+        if (FLAGS & F_COPY_IN) {  // the input state, as loaded
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (lane + kLanes * i < n) ((V *)P.copy_out)[base + lane + kLanes * i] = nxt[i];
+        }
         if (li + 1 < count) {
             const int64_t nl = line + 1;
             x_load_line<R, Q>(src, nl, P.nlines, n, lane, nxt);

@@ -41,6 +41,32 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
                 P.adj_out[2 * blockIdx.x + 1] = c;
             }
         }
+        if ((FLAGS & F_ADJ_N) && P.adj_done) {
+            // the last workgroup to finish reduces every workgroup's partials,
+            // in the fixed order of the separate reduce kernel
+            __shared__ int last;
+            if (threadIdx.x == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const int done = __hip_atomic_fetch_add(P.adj_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = done == (int)gridDim.x - 1;
+            }
+            __syncthreads();
+            if (last && wave == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                double sw = 0.0, sg = 0.0;
+                for (int i = lane; i < (int)gridDim.x; i += kLanes) {
+                    sw += __hip_atomic_load(P.adj_out + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sg += __hip_atomic_load(P.adj_out + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                sw = wave_sum(sw);
+                sg = wave_sum(sg);
+                if (lane == 0) {
+                    if (P.adj_dsched) *P.adj_dsched = P.adj_coeff * sw;
+                    if (P.adj_dg) *P.adj_dg += P.dt * sg;
+                    __hip_atomic_store(P.adj_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
     }
 }
 
@@ -92,6 +118,7 @@ static hipError_t launch_x_mode(const SweepParams &P, int flags, int Q, const vo
     switch (flags) {
     case 0: return launch_x_flags<R, MODE, 0>(P, Q, tab, s);
     case F_FUSE_N: return launch_x_flags<R, MODE, F_FUSE_N>(P, Q, tab, s);
+    case F_FUSE_N | F_COPY_IN: return launch_x_flags<R, MODE, F_FUSE_N | F_COPY_IN>(P, Q, tab, s);
     case F_ADJ_N: return launch_x_flags<R, MODE, F_ADJ_N>(P, Q, tab, s);
     default: return hipErrorInvalidValue;
     }

@@ -130,8 +130,12 @@ def test_autograd_fp32_gradient_error(gp):
     assert err < 1e-3
 
 
-def test_step_record_stores_each_step_input(gp):
-    n, dx, dt, omega, g, m = (48, 40, 36), (0.2, 0.2, 0.25), 1e-3, (1.0, 1.5, 2.0), 60.0, 5
+@pytest.mark.parametrize("n", [(48, 40, 36), (64, 50), (128, 30, 12)])
+def test_step_record_stores_each_step_input(gp, n):
+    # the x sweep writes the recorded state as it loads (1D/2D/unfused 3D); the
+    # fused 3D sweep is preceded by a copy
+    dx = (0.2, 0.2, 0.25)[:len(n)]
+    dt, omega, g, m = 1e-3, (1.0, 1.5, 2.0)[:len(n)], 60.0, 5
     psi0 = to_dev(inputs.noisy_gaussian(n, dx, omega, 44))
     plan = gp.Plan(n, dx, dt, gp.GP_REAL, omega, g)
     psi = psi0.clone()
