@@ -339,6 +339,55 @@ __device__ __forceinline__ cp<R> potential_adjoint(cp<R> lam, int64_t t, const V
     return {l.re + k2 * psi.re, l.im + k2 * psi.im};
 }
 
+// potential_adjoint on Q values at points q0 + qs i (those below n), with the
+// forward state already loaded (st), the series branch shared by all values as
+// in potential_substep_n and the sums accumulated in order of i.
+template <typename R, int MODE, int FLAGS, int Q, typename V>
+__device__ __forceinline__ void potential_adjoint_q(cp<R> (&lam)[Q], const V (&st)[Q], int q0, int qs, int64_t n,
+                                                    const SweepParams &P, const LineCtx<R> &L, double &acc_w,
+                                                    double &acc_g)
+{
+    using T = Taylor<R>;
+    cp<R> psi[Q];
+    R x[Q], d[Q], sn[Q], h[Q];
+    bool big = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        psi[i] = from_v<R>(st[i]);
+        x[i] = R(((double)(q0 + qs * i) + P.x0[0]) * P.dx[0]);
+        d[i] = psi[i].re * psi[i].re + psi[i].im * psi[i].im;
+        const R t = R(P.dt) * (L.vperp + L.hw0 * x[i] * x[i] + R(P.g) * d[i]), t2 = t * t;
+        big |= !(fabs(t) <= R(0.125));
+        if (sizeof(R) == 8) {
+            sn[i] = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * (T::s7 + t2 * (T::s9 + t2 * T::s11))));
+            h[i] = t2 * (T::h2 + t2 * (T::h4 + t2 * (T::h6 + t2 * (T::h8 + t2 * T::h10))));
+        } else {
+            sn[i] = t + t * t2 * (T::s3 + t2 * (T::s5 + t2 * T::s7));
+            h[i] = t2 * (T::h2 + t2 * (T::h4 + t2 * T::h6));
+        }
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R t = R(P.dt) * (L.vperp + L.hw0 * x[i] * x[i] + R(P.g) * d[i]);
+            if (!(fabs(t) <= R(0.125))) phase_r(t, &sn[i], &h[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const cp<R> u = rotate(psi[i], sn[i], h[i], R(1));  // u = psi e^{-i theta}
+        const R w = lam[i].re * u.im - lam[i].im * u.re;   // Im(conj(lam) u)
+        const R k2 = R(2) * R(P.dt) * R(P.g) * w;
+        const R xs2 = P.sched_axis == 0 ? x[i] * x[i] : (P.sched_axis == 1 ? L.ysq : L.zsq);
+        if (q0 + qs * i < n) {
+            acc_w += (double)w * (double)xs2;
+            acc_g += (double)w * (double)d[i];
+        }
+        const cp<R> l = rotate(lam[i], sn[i], h[i], R(-1));  // lam e^{+i theta}
+        lam[i] = {l.re + k2 * psi[i].re, l.im + k2 * psi[i].im};
+    }
+}
+
 // Wavefront sums of the epilogue accumulators, written to partial slot g.
 template <typename R, int FLAGS>
 __device__ __forceinline__ void write_partials(const SweepParams &P, int lane, double nacc,

@@ -275,6 +275,16 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
             for (int i = 0; i < Q; ++i)
                 if (lane + kLanes * i < n) ((V *)P.copy_out)[base + lane + kLanes * i] = nxt[i];
         }
+        // the adjoint's forward state, requested before the solve so that its
+        // latency overlaps it (clamped in-bounds addresses; used below n only)
+        V stv[(FLAGS & F_ADJ_N) ? Q : 1];
+        if constexpr ((FLAGS & F_ADJ_N) != 0) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int64_t q = lane + kLanes * i;
+                stv[i] = state[base + (q < n ? q : n - 1)];
+            }
+        }
         if (li + 1 < count) {
             const int64_t nl = line + 1;
             x_load_line<R, Q>(src, nl, P.nlines, n, lane, nxt);
@@ -297,13 +307,14 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
             for (int i = 0; i < Q; ++i) u[i] = from_v<R>(xl[pad(lane + kLanes * i)]);
             wave_lds_sync();
         }
+        if constexpr ((FLAGS & F_ADJ_N) != 0)
+            potential_adjoint_q<R, MODE, FLAGS, Q>(u, stv, lane, kLanes, n, P, L, acc_w, acc_g);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t q = lane + kLanes * i;
             if (q < n) {
-                cp<R> w = u[i];
+                const cp<R> w = u[i];
                 if (FLAGS & F_NORM_OUT) nacc += (double)w.re * (double)w.re + (double)w.im * (double)w.im;
-                if (FLAGS & F_ADJ_N) w = potential_adjoint<R, MODE, FLAGS>(w, q, state, base + q, P, L, acc_w, acc_g);
                 dst[base + q] = to_v<V>(w);
             }
         }
