@@ -29,11 +29,18 @@ constexpr int kXYWaves = 4;  // wavefronts per workgroup = rows per block of the
 constexpr int kXYAhead = 1;  // blocks whose rows are loaded ahead
 constexpr int kXYMaxScan = 3;  // x scan steps the fused kernel supports
 
-// Tile slot of point q of a row: the low three bits (one 128-byte group of
-// 16-byte values) are permuted by the next three, so the coalesced row
+// Tile slot of point q of a row, for values of E bytes.  E = 16: the low three
+// bits (one 128-byte group) are permuted by the next three, so the coalesced row
 // (lane + 64 i), the solver's consecutive points (lane Q + i) and the column
-// reads each hit eight distinct 16-byte bank groups per eight lanes.
-__device__ __forceinline__ int xy_slot(int q) { return q ^ ((q >> 3) & 7); }
+// reads each hit eight distinct 16-byte bank groups per eight lanes.  E = 8:
+// the low two bits are permuted by bits 4-5, so each sixteen lanes of those
+// patterns hit sixteen distinct 8-byte bank pairs (the 16-byte permutation
+// leaves the consecutive-points pattern two-way conflicted there).
+template <int E> __device__ __forceinline__ int xy_slot(int q)
+{
+    if constexpr (E == 8) return q ^ ((q >> 4) & 3);
+    return q ^ ((q >> 3) & 7);
+}
 
 // Row y = jb B + w of plane k (zeros past the plane or past block j1).
 template <typename R, int Q>
@@ -104,17 +111,17 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
                 if (XFLAGS & F_FUSE_N) potential_substep_q<R, MODE, XFLAGS, Q>(u, lane, kLanes, PX, L);
                 if (Q > 1) {  // coalesced -> Q consecutive points per lane
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) row[xy_slot(lane + kLanes * i)] = to_v<V>(u[i]);
+                    for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane + kLanes * i)] = to_v<V>(u[i]);
                     wave_lds_sync();
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot(lane * Q + i)]);
+                    for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot<(int)sizeof(V)>(lane * Q + i)]);
                 }
                 x_line_solve<R, MODE, Q, kXYMaxScan>(PX, KX, S, lane, u);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(u[i]);
+                for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane * Q + i)] = to_v<V>(u[i]);
             } else {  // rows past the plane are the y solver's zero rows
 #pragma unroll
-                for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(zero);
+                for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane * Q + i)] = to_v<V>(zero);
             }
             // the next rows are requested only now: the vector memory counter is
             // in order, so waiting for the x solve's table loads would otherwise
@@ -124,7 +131,7 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy(SweepParams PX, S
             if (w < cw) {
                 V buf[B];
 #pragma unroll
-                for (int r = 0; r < B; ++r) buf[r] = tile[r][xy_slot(w * kLanes + lane)];
+                for (int r = 0; r < B; ++r) buf[r] = tile[r][xy_slot<(int)sizeof(V)>(w * kLanes + lane)];
                 Y.template process<false>(buf, j);  // tile rows are zero off the grid
             }
             __syncthreads();
@@ -244,18 +251,18 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
             if (XFLAGS & F_FUSE_N) potential_substep_q<R, MODE, XFLAGS, Q>(u, lane, kLanes, PX, L);
             if (Q > 1) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) row[xy_slot(lane + kLanes * i)] = to_v<V>(u[i]);
+                for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane + kLanes * i)] = to_v<V>(u[i]);
                 wave_lds_sync();
 #pragma unroll
-                for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot(lane * Q + i)]);
+                for (int i = 0; i < Q; ++i) u[i] = from_v<R>(row[xy_slot<(int)sizeof(V)>(lane * Q + i)]);
                 wave_lds_sync();
             }
             x_line_solve<R, MODE, Q, kXYMaxScan>(PX, KX, S, lane, u);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(u[i]);
+            for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane * Q + i)] = to_v<V>(u[i]);
         } else {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) row[xy_slot(lane * Q + i)] = to_v<V>(zero);
+            for (int i = 0; i < Q; ++i) row[xy_slot<(int)sizeof(V)>(lane * Q + i)] = to_v<V>(zero);
         }
     };
 
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
         if (w < cw) {
             cp<R> v[B];
 #pragma unroll
-            for (int r = 0; r < B; ++r) v[r] = from_v<R>(tile[j & 1][r][xy_slot(w * kLanes + lane)]);
+            for (int r = 0; r < B; ++r) v[r] = from_v<R>(tile[j & 1][r][xy_slot<(int)sizeof(V)>(w * kLanes + lane)]);
             // one copy of the y step per window slot, so the slot index is a constant
             static_for<DW + 1>([&](auto U) {
                 if (u == decltype(U)::value) Y.template process<decltype(U)::value>(v, j, taby, dst);
