@@ -54,6 +54,11 @@ constexpr int kCtrHead = 0, kCtrError = 1, kCtrFirstProblem = 4;
 constexpr int kBatchWaves = 4;                 // wavefronts per workgroup of the batched kernels
 constexpr unsigned kSpinLimit = 1u << 22;      // default bound of a dependency wait (polls, ~0.3 s)
 
+// y lines solved as tiles by the scan solver: up to kBatchTileMaxQ points per
+// lane (longer ones take the windowed items).
+constexpr int kBatchTileMaxQ = 8;
+inline bool batch_tiles(const AxisPlan &Y) { return Y.xq > 0 && Y.xq <= kBatchTileMaxQ; }
+
 struct BatchConfig {
     int persistent = 0;  // 1: one launch for all steps (real time only)
     int lines = 4;       // x lines per item
@@ -398,7 +403,7 @@ static gp_status prepare(gp_batch *b, void *const *psis)
         for (int64_t l = 0; l < ny; l += b->cfg.lines)
             xk[k].push_back({k, 0, 1, (int)std::min<int64_t>(b->cfg.lines, ny - l), l});
         nx_per[k] = (int)xk[k].size();
-        if (p->ax[1].xq > 0) {  // scan-solved y lines: items of whole tiles, one norm partial each
+        if (batch_tiles(p->ax[1])) {  // scan-solved y lines: items of whole tiles, one norm partial each
             const int64_t tl = b->prec == GP_C128 ? col_tile_lines<double>() : col_tile_lines<float>();
             int64_t per = std::max<int64_t>(b->cfg.lines, (nx + p->n_norm - 1) / p->n_norm);
             per = (per + tl - 1) / tl * tl;
@@ -426,7 +431,7 @@ static gp_status prepare(gp_batch *b, void *const *psis)
         xi.insert(xi.end(), xk[k].begin(), xk[k].end());
         yi.insert(yi.end(), yk[k].begin(), yk[k].end());
         const gp_plan *p = b->plans[k];
-        if (p->ax[0].scan_steps > 3 || (p->ax[1].xq > 0 && p->ax[1].scan_steps > 3)) b->smax = 6;
+        if (p->ax[0].scan_steps > 3 || (batch_tiles(p->ax[1]) && p->ax[1].scan_steps > 3)) b->smax = 6;
     }
     gp_status st = upload((void **)&b->d_px, px.data(), px.size() * sizeof(SweepParams));
     if (st == GP_OK) st = upload((void **)&b->d_py, py.data(), py.size() * sizeof(SweepParams));
@@ -550,7 +555,7 @@ static gp_status check_error_flag(gp_batch *b, hipStream_t s)
 // y-sweep half of the check runs on the host before any HIP call.
 static gp_status batch_y_supported(const AxisPlan &Y)
 {
-    if (Y.n <= (int64_t)kColMaxQ * kLanes) return GP_OK;  // scan solver
+    if (Y.n <= (int64_t)kBatchTileMaxQ * kLanes) return GP_OK;  // scan solver
     if (Y.K < 0 || Y.B != 4 || Y.D < 1 || Y.D > 8)
         return set_error("batched y sweep needs a windowed solve of 1..8 blocks (dt/dx^2 too large)"),
                GP_EUNSUPPORTED;
@@ -563,7 +568,7 @@ static gp_status batch_supports(const gp_plan *p, int max_lds)
     if (X.xq < 1 || X.xq > kXMaxQ) return set_error("batched x sweep needs 1 <= nx <= 1024"), GP_EUNSUPPORTED;
     const gp_status st = batch_y_supported(Y);
     if (st != GP_OK) return st;
-    const size_t ring = Y.xq > 0 ? (p->prec == GP_C128 ? col_tile_lds_bytes<double>(Y.xq)
+    const size_t ring = batch_tiles(Y) ? (p->prec == GP_C128 ? col_tile_lds_bytes<double>(Y.xq)
                                                        : col_tile_lds_bytes<float>(Y.xq))
                         : p->prec == GP_C128 ? window_lds_bytes<double, kStrided, 4>(Y.L)
                                              : window_lds_bytes<float, kStrided, 4>(Y.L);
@@ -634,7 +639,7 @@ gp_status gp_batch_create(gp_batch **out, int count, const int64_t *n, const dou
         }
         b->plans.push_back(p);
         b->qmax = std::max(b->qmax, p->ax[0].xq);
-        b->qmax_y = std::max(b->qmax_y, p->ax[1].xq);
+        if (batch_tiles(p->ax[1])) b->qmax_y = std::max(b->qmax_y, p->ax[1].xq);
         st = batch_supports(p, max_lds);
         if (st != GP_OK) {
             gp_batch_destroy(b);

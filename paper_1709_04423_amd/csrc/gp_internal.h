@@ -198,7 +198,8 @@ hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, cons
 // than 0): flags 0 or F_NORM_OUT.
 hipError_t launch_col_scan(const gp_plan *p, int axis, const SweepParams &P, int flags, const void *tab,
                            hipStream_t s);
-constexpr int kColMaxQ = 8;  // longest strided line of the scan solver: 64 kColMaxQ points
+constexpr int kColMaxQ = 16;  // longest strided line of the scan solver: 64 kColMaxQ points
+constexpr int kXLdsQ = 16;    // from this many points per lane the scan kernels keep the table rows in LDS
 // Fused x and y sweeps of a 3D step (src -> dst, x flags as for the x sweep).
 hipError_t launch_xy(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
 size_t xy_lds_bytes(const gp_plan *p, int variant);

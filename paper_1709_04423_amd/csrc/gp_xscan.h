@@ -25,6 +25,8 @@
 // layout), as in the other sweeps.
 #pragma once
 
+#include <type_traits>
+
 #include "gp_sweep_common.h"
 
 namespace gp {
@@ -151,9 +153,56 @@ __device__ __forceinline__ void x_load_line(const typename CT<R>::V *src, int64_
 // each multiplier would be one more memory round trip per line, in sequence.
 template <typename R, int Q, int SMAX> struct XConsts {
     using V = typename CT<R>::V;
-    V c[Q], b[Q], blo[Q];
+    V c_[Q], b_[Q], blo_[Q];
     V mf[SMAX], mb[SMAX];
+    __device__ __forceinline__ V c(int i) const { return c_[i]; }
+    __device__ __forceinline__ V b(int i) const { return b_[i]; }
+    __device__ __forceinline__ V blo(int i) const { return blo_[i]; }
 };
+
+// The same constants with the table rows in LDS, one copy per workgroup (all
+// its wavefronts solve lines of one axis): for 16 points per lane the rows
+// would take 48 registers (complex64) or 192 (complex128) per lane.  Row k of
+// point i of lane L at kc[(k Q + i) 64 + L]: consecutive lanes, no conflicts.
+template <typename R, int Q, int SMAX> struct XConstsLds {
+    using V = typename CT<R>::V;
+    const V *kc;
+    int lane;
+    V mf[SMAX], mb[SMAX];
+    __device__ __forceinline__ V c(int i) const { return kc[(0 * Q + i) * kLanes + lane]; }
+    __device__ __forceinline__ V b(int i) const { return kc[(1 * Q + i) * kLanes + lane]; }
+    __device__ __forceinline__ V blo(int i) const { return kc[(2 * Q + i) * kLanes + lane]; }
+};
+
+// Fills a workgroup's LDS rows (3 Q 64 values) for XConstsLds; the caller
+// synchronises the workgroup afterwards.
+template <typename R, int Q>
+__device__ __forceinline__ void x_rows_to_lds(const SweepParams &P, const typename CT<R>::V *__restrict__ tab,
+                                              typename CT<R>::V *kc)
+{
+    using V = typename CT<R>::V;
+    for (int t = threadIdx.x; t < Q * kLanes; t += blockDim.x) {
+        const int i = t / kLanes, L = t % kLanes;
+        V c, b, blo;
+        row_of<R>(P, tab, (int64_t)L * Q + i, c, b, blo);
+        kc[(0 * Q + i) * kLanes + L] = c;
+        kc[(1 * Q + i) * kLanes + L] = b;
+        kc[(2 * Q + i) * kLanes + L] = blo;
+    }
+}
+
+template <typename R, int Q, int SMAX>
+__device__ __forceinline__ void x_mul_load(const SweepParams &P, const typename CT<R>::V *__restrict__ xmul, int lane,
+                                           typename CT<R>::V (&mf)[SMAX], typename CT<R>::V (&mb)[SMAX])
+{
+    const int last = P.scan_steps > 0 ? P.scan_steps - 1 : 0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {  // unconditional loads (steps past S are not used)
+        const int r = s < last ? s : last;
+        mf[s] = xmul[r * kLanes + lane];
+        mb[s] = xmul[(6 + r) * kLanes + lane];
+    }
+}
 
 template <typename R, int Q, int SMAX>
 __device__ __forceinline__ void x_consts_load(const SweepParams &P, const typename CT<R>::V *__restrict__ tab,
@@ -162,22 +211,15 @@ __device__ __forceinline__ void x_consts_load(const SweepParams &P, const typena
 {
     const int64_t q0 = (int64_t)lane * Q;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) row_of<R>(P, tab, q0 + i, K.c[i], K.b[i], K.blo[i]);
-    const int last = P.scan_steps > 0 ? P.scan_steps - 1 : 0;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {  // unconditional loads (steps past S are not used)
-        const int r = s < last ? s : last;
-        K.mf[s] = xmul[r * kLanes + lane];
-        K.mb[s] = xmul[(6 + r) * kLanes + lane];
-    }
+    for (int i = 0; i < Q; ++i) row_of<R>(P, tab, q0 + i, K.c_[i], K.b_[i], K.blo_[i]);
+    x_mul_load<R, Q, SMAX>(P, xmul, lane, K.mf, K.mb);
 }
 
 // Solves one line held as Q consecutive points per lane (u, in the potential
 // substep's output) and leaves the CN sweep's result in u, same layout.  Uses
 // only registers and cross-lane shuffles; S <= SMAX scan steps.
-template <typename R, int MODE, int Q, int SMAX>
-__device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts<R, Q, SMAX> &K, int S, int lane,
-                                             cp<R> (&u)[Q])
+template <typename R, int MODE, int Q, int SMAX, typename KC>
+__device__ __forceinline__ void x_line_solve(const SweepParams &P, const KC &K, int S, int lane, cp<R> (&u)[Q])
 {
     const cp<R> zero = {R(0), R(0)};
     cp<R> left = shfl_up_c(u[Q - 1], 1);
@@ -186,18 +228,21 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts
     if (lane == kLanes - 1) right = zero;
 
     // forward: f_p = c'_p rhs_p = -a_p rhs_p, y_p = a_p y_{p-1} + f_p
-    cp<R> f[Q], ac[Q];
+    cp<R> f[Q];
+    auto ac = [&](int i) -> cp<R> {
+        const auto c = K.c(i);
+        return {-c.x, MODE == GP_IMAG ? R(0) : -c.y};
+    };
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const cp<R> um1 = i == 0 ? left : u[i - 1];
         const cp<R> up1 = i == Q - 1 ? right : u[i + 1];
-        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, K.b[i], K.blo[i]);
-        f[i] = kmul<MODE>(from_v<R>(K.c[i]), rhs);
-        ac[i] = {-K.c[i].x, MODE == GP_IMAG ? R(0) : -K.c[i].y};
+        const cp<R> rhs = cn_rhs<MODE, R>(um1, u[i], up1, K.b(i), K.blo(i));
+        f[i] = kmul<MODE>(from_v<R>(K.c(i)), rhs);
     }
     cp<R> F = f[0];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac[i], F, f[i]);
+    for (int i = 1; i < Q; ++i) F = kfma<MODE>(ac(i), F, f[i]);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
         if (s < S) {  // uniform
@@ -209,13 +254,13 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts
     if (lane == 0) y = zero;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        y = kfma<MODE>(ac[i], y, f[i]);
+        y = kfma<MODE>(ac(i), y, f[i]);
         f[i] = y;
     }
     // backward: u'_p = a_p u'_{p+1} + y_p
     cp<R> G = f[Q - 1];
 #pragma unroll
-    for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac[i], G, f[i]);
+    for (int i = Q - 2; i >= 0; --i) G = kfma<MODE>(ac(i), G, f[i]);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
         if (s < S) {  // uniform
@@ -227,7 +272,7 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts
     if (lane == kLanes - 1) v = zero;
 #pragma unroll
     for (int i = Q - 1; i >= 0; --i) {
-        v = kfma<MODE>(ac[i], v, f[i]);
+        v = kfma<MODE>(ac(i), v, f[i]);
         u[i] = v;
     }
 }
@@ -242,11 +287,13 @@ __device__ __forceinline__ void x_line_solve(const SweepParams &P, const XConsts
 // One wavefront solves lines first .. first+count-1 (those below P.nlines),
 // adding its epilogue sums to nacc / acc_w / acc_g.
 // xl: this wavefront's LDS buffer of x_lds_bytes<R>(Q) bytes.
-template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
+// KLDS: the table rows come from the workgroup's LDS copy kc (XConstsLds).
+template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6, bool KLDS = false>
 __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
                                             typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
                                             const typename CT<R>::V *__restrict__ state, int64_t first, int count,
-                                            double &nacc, double &acc_w, double &acc_g, typename CT<R>::V *xl)
+                                            double &nacc, double &acc_w, double &acc_g, typename CT<R>::V *xl,
+                                            const typename CT<R>::V *kc = nullptr)
 {
     using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
@@ -254,8 +301,14 @@ __device__ __forceinline__ void x_scan_wave(const SweepParams &P, const typename
     auto pad = [](int q) { return q + q / Q; };  // slot of point q in xl
     const int S = P.scan_steps;
     const cp<R> zero = {R(0), R(0)};
-    XConsts<R, Q, SMAX> K;  // scan steps S <= SMAX
-    x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+    std::conditional_t<KLDS, XConstsLds<R, Q, SMAX>, XConsts<R, Q, SMAX>> K;  // scan steps S <= SMAX
+    if constexpr (KLDS) {
+        K.kc = kc;
+        K.lane = lane;
+        x_mul_load<R, Q, SMAX>(P, (const V *)P.xmul, lane, K.mf, K.mb);
+    } else {
+        x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+    }
     const double renorm = (FLAGS & F_RENORM) ? 1.0 / sqrt(P.dV * P.norm_total[0]) : 1.0;
     V nxt[Q];  // the next line's values, loaded while the current one is solved
     x_load_line<R, Q>(src, first, P.nlines, n, lane, nxt);
@@ -341,17 +394,24 @@ __device__ __forceinline__ void col_load_line(const typename CT<R>::V *src, cons
     }
 }
 
-template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6>
+template <typename R, int MODE, int FLAGS, int Q, int SMAX = 6, bool KLDS = false>
 __device__ __forceinline__ void col_scan_wave(const SweepParams &P, const typename CT<R>::V *src,
                                               typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ tab,
-                                              int64_t first, int count, int64_t lstep, double &nacc)
+                                              int64_t first, int count, int64_t lstep, double &nacc,
+                                              const typename CT<R>::V *kc = nullptr)
 {
     using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int64_t n = P.n;
     const cp<R> zero = {R(0), R(0)};
-    XConsts<R, Q, SMAX> K;
-    x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+    std::conditional_t<KLDS, XConstsLds<R, Q, SMAX>, XConsts<R, Q, SMAX>> K;
+    if constexpr (KLDS) {
+        K.kc = kc;
+        K.lane = lane;
+        x_mul_load<R, Q, SMAX>(P, (const V *)P.xmul, lane, K.mf, K.mb);
+    } else {
+        x_consts_load<R, Q, SMAX>(P, tab, (const V *)P.xmul, lane, K);
+    }
     V nxt[Q];
     col_load_line<R, Q>(src, P, first, lane, nxt);
 #pragma unroll 1

@@ -11,12 +11,22 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_x_scan(SweepParams P,
                                                                    const typename CT<R>::V *__restrict__ tab,
                                                                    const typename CT<R>::V *__restrict__ state)
 {
+    using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
-    __shared__ typename CT<R>::V xl[kXWaves][kLanes * (Q + 1)];
+    __shared__ V xl[kXWaves][kLanes * (Q + 1)];
     double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
-    x_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw,
-                                   P.xlpw, nacc, acc_w, acc_g, xl[wave]);
+    if constexpr (Q >= kXLdsQ) {  // table rows in LDS, one copy for the workgroup
+        __shared__ V kc[3 * Q * kLanes];
+        x_rows_to_lds<R, Q>(P, tab, kc);
+        __syncthreads();
+        x_scan_wave<R, MODE, FLAGS, Q, SMAX, true>(P, src, dst, tab, state,
+                                                   ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw, P.xlpw, nacc,
+                                                   acc_w, acc_g, xl[wave], kc);
+    } else {
+        x_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, state, ((int64_t)blockIdx.x * kXWaves + wave) * P.xlpw,
+                                             P.xlpw, nacc, acc_w, acc_g, xl[wave]);
+    }
     if (FLAGS & (F_NORM_OUT | F_ADJ_N)) {
         __shared__ double red[kXWaves][3];
         nacc = wave_sum(nacc);
@@ -132,11 +142,19 @@ __global__ __launch_bounds__(kLanes *kXWaves) void k_sweep_col_scan(SweepParams 
                                                                      typename CT<R>::V *dst,
                                                                      const typename CT<R>::V *__restrict__ tab)
 {
+    using V = typename CT<R>::V;
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     double nacc = 0.0;
-    col_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, (int64_t)blockIdx.x * kXWaves * P.xlpw + wave, P.xlpw,
-                                           kXWaves, nacc);
+    const int64_t first = (int64_t)blockIdx.x * kXWaves * P.xlpw + wave;
+    if constexpr (Q >= kXLdsQ) {
+        __shared__ V kc[3 * Q * kLanes];
+        x_rows_to_lds<R, Q>(P, tab, kc);
+        __syncthreads();
+        col_scan_wave<R, MODE, FLAGS, Q, SMAX, true>(P, src, dst, tab, first, P.xlpw, kXWaves, nacc, kc);
+    } else {
+        col_scan_wave<R, MODE, FLAGS, Q, SMAX>(P, src, dst, tab, first, P.xlpw, kXWaves, nacc);
+    }
     if (FLAGS & F_NORM_OUT) {
         __shared__ double red[kXWaves];
         nacc = wave_sum(nacc);
@@ -172,6 +190,7 @@ static hipError_t launch_col_flags(const SweepParams &P, int Q, const void *tab,
     case 2: launch_col_q<R, MODE, FLAGS, 2>(P, tab, s); break;
     case 4: launch_col_q<R, MODE, FLAGS, 4>(P, tab, s); break;
     case 8: launch_col_q<R, MODE, FLAGS, 8>(P, tab, s); break;
+    case 16: launch_col_q<R, MODE, FLAGS, 16>(P, tab, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
