@@ -74,6 +74,10 @@ CASES_FP64 = [
     ((40, 301, 20), (0.2, 0.04, 0.3), 2e-4, (1.0, 1.0, 2.0), 20.0, 2),
     ((50, 701), (0.2, 0.03), 2e-4, (1.0, 1.0), 20.0, 3),
     ((24, 20, 517), (0.3, 0.3, 0.025), 1e-4, (1.0, 1.0, 1.0), 20.0, 2),
+    # lines of 513-1024 points: the scan solvers with their table rows in LDS (x, and 2D y)
+    ((1000,), (0.02,), 1e-4, (1.0,), 10.0, 3),
+    ((700, 30), (0.03, 0.3), 2e-4, (1.0, 1.0), 20.0, 2),
+    ((60, 1000), (0.3, 0.02), 1e-4, (1.0, 1.0), 20.0, 2),
     # x lines longer than the scan kernel takes (64 x 16 points): windowed x solver
     ((2000,), (0.02,), 1e-4, (1.0,), 10.0, 3),
     ((1500, 12), (0.02, 0.3), 1e-4, (1.0, 1.0), 10.0, 2),
