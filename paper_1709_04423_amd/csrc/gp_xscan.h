@@ -216,8 +216,10 @@ __device__ __forceinline__ void x_consts_load(const SweepParams &P, const typena
 }
 
 // Solves one line held as Q consecutive points per lane (u, in the potential
-// substep's output) and leaves the CN sweep's result in u, same layout.  Uses
-// only registers and cross-lane shuffles; S <= SMAX scan steps.
+// substep's output) and leaves the CN sweep's result in u, same layout.  Data
+// moves only through registers and cross-lane shuffles; the table rows come
+// from K (XConsts: registers, XConstsLds: the workgroup's LDS copy); S <= SMAX
+// scan steps.
 template <typename R, int MODE, int Q, int SMAX, typename KC>
 __device__ __forceinline__ void x_line_solve(const SweepParams &P, const KC &K, int S, int lane, cp<R> (&u)[Q])
 {
