@@ -165,7 +165,8 @@ gp_status gp_observables(gp_plan *plan, const void *psi, gp_obs *out, void *stre
 gp_status gp_plan_set_step(gp_plan *plan, int64_t step);
 gp_status gp_plan_get_info(const gp_plan *plan, gp_plan_info *info);
 
-/* 3D forward steps: enable (1, the default) or disable (0) the fused x+y sweep.
+/* 3D forward steps: enable (1 or 2, the default 2) or disable (0) the fused x+y
+ * sweep.
  * The x and y Crank-Nicolson substeps of the step (program summary, "Solution
  * method") act plane by plane, so where the plan's shape allows (x extent 128,
  * 192 or 256, and a y window of 2..4 blocks that fits in LDS) one kernel reads
