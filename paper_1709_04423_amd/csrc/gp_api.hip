@@ -178,11 +178,9 @@ AxisPlan preview_axis(int64_t n, int64_t nlines, double dx, double dt, gp_mode m
 }
 
 // x sweep with one wavefront per line: Q = points per lane (power of two,
-// n <= 64 Q <= 64 kXMaxQ), scan steps S = smallest with Q 2^S > Kmin (full
-// scan, S = 6, when that is not below 64 lanes), and the first point from
-// which the stored table rows no longer change.
-template <typename T>
-static void x_scan_setup(AxisPlan &A, const std::vector<std::complex<long double>> &c, gp_mode mode)
+// n <= 64 Q <= 64 kXMaxQ) and scan steps S = smallest with Q 2^S > Kmin (full
+// scan, S = 6, when that is not below 64 lanes).
+static void x_scan_setup(AxisPlan &A)
 {
     A.xq = 0;
     int Q = 1;
@@ -196,6 +194,13 @@ static void x_scan_setup(AxisPlan &A, const std::vector<std::complex<long double
     int S = 0;
     while (S < 6 && (int64_t)Q * (1 << S) <= A.kmin) ++S;
     A.scan_steps = S;
+}
+
+// The first point from which the stored table rows no longer change (the
+// Thomas factors have converged to the table's rounding), and that row.
+template <typename T>
+static void const_row_setup(AxisPlan &A, const std::vector<std::complex<long double>> &c, gp_mode mode)
+{
     std::vector<T> rows;
     table_rows<T>(c, A.n + 1, A.r, mode, false, rows);
     int64_t qc = A.n;
@@ -555,19 +560,14 @@ static gp_status create_plan(gp_plan **out, int geom, int ndim, const int64_t *n
         thomas_c(A.n, A.r, mode, cs[a], A.rho);
         // strided axes stream blocks of 4 rows per wavefront
         choose_window(A, prec, a == 0 ? kBlock : 4, a == 0);
-        if (a == 0) {
-            if (prec == GP_C128)
-                x_scan_setup<double>(A, cs[a], mode);
-            else
-                x_scan_setup<float>(A, cs[a], mode);
-            if (A.xq > 0 && A.npad < (int64_t)A.xq * kLanes) A.npad = (int64_t)A.xq * kLanes;
-        } else if (a == 1 && ndim == 2 && A.n <= (int64_t)kColMaxQ * kLanes) {
-            // a 2D grid's y lines are too few for the windowed solver to fill
-            // the device: one wavefront per line with the scan solver instead
-            if (prec == GP_C128)
-                x_scan_setup<double>(A, cs[a], mode);
-            else
-                x_scan_setup<float>(A, cs[a], mode);
+        if (prec == GP_C128)
+            const_row_setup<double>(A, cs[a], mode);
+        else
+            const_row_setup<float>(A, cs[a], mode);
+        // a 2D grid's y lines are too few for the windowed solver to fill the
+        // device: one wavefront per line with the scan solver instead
+        if (a == 0 || (a == 1 && ndim == 2 && A.n <= (int64_t)kColMaxQ * kLanes)) {
+            x_scan_setup(A);
             if (A.xq > 0 && A.npad < (int64_t)A.xq * kLanes) A.npad = (int64_t)A.xq * kLanes;
         }
     }

@@ -155,44 +155,94 @@ template <int N, typename F> __device__ __forceinline__ void static_for(F &&f)
 // the window holds the eliminated values of the last DW + 1 blocks of four rows,
 // and the block loop is unrolled by DW + 1 so block j's values live in slot
 // u = (j - j0) mod (DW + 1), a compile-time index in every unrolled copy.
-// The arithmetic is WindowSweep::process's (same order, same table rows), only
-// the ring moved from LDS to registers.
+// The elimination is WindowSweep::process's (same order, same table rows), only
+// the ring moved from LDS to registers.  Away from the line's start and end
+// every table row a block touches is the constant row (the Thomas factors have
+// converged to rounding: rows of points q_const .. n-1 are equal bit for bit),
+// and CR = true takes it from registers instead of the table: no loads and no
+// waits for them in the steady state.  With a constant c' the windowed back
+// substitution also splits by blocks: x_{mB} = S_m + (-c')^B x_{(m+1)B}, where
+// S_m (the block's back substitution from a zero after it) is formed once when
+// block m is eliminated.  The output block then costs DW - 1 of those steps and
+// B - 1 single-point steps instead of (DW + 1) B - 1 of the latter -- the same
+// truncated window, summed in another order.  Not in complex128 real time: the
+// DW + 1 sums would push that kernel past 256 registers (one wavefront per SIMD).
 template <typename R, int MODE, int DW> struct YRegSolver {
     using V = typename CT<R>::V;
     static constexpr int B = kXYWaves;
+    static constexpr bool kSums = sizeof(R) == 4 || MODE == GP_IMAG;
     cp<R> d[DW + 1][B];
+    cp<R> bs[kSums ? DW + 1 : 1];  // S_m of the block in each slot
     cp<R> um1, u0, dprev;
     int o_lo, o_hi;
     int64_t base, stride, n;
+    V rc, rb, rblo;  // the constant row (c', beta, beta_lo)
+    cp<R> cB;        // (-c')^B
+
+    // field k of table row t (row t belongs to point t - 1)
+    template <bool CR> __device__ __forceinline__ V row(const V *__restrict__ tab, int64_t t, int k) const
+    {
+        if constexpr (CR) return k == 0 ? rc : (k == 1 ? rb : rblo);
+        return tab[3 * t + k];
+    }
+
+    // whether block j's rows are all the constant row: elimination rows jB ..
+    // jB+B-1 and back-substitution rows (j-DW)B+1 .. jB+B-1 within q_const+1 .. n
+    __device__ __forceinline__ static bool const_rows(int j, int64_t q_const, int64_t n)
+    {
+        return (int64_t)(j - DW) * B >= q_const && (int64_t)j * B + B - 1 <= n;
+    }
 
     // block j (rows jB .. jB+3 in v), stored in slot U; writes output block j - DW
-    template <int U>
+    template <int U, bool CR>
     __device__ __forceinline__ void process(const cp<R> (&v)[B], int j, const V *__restrict__ tab, V *dst)
     {
         static_for<B>([&](auto K) {  // eliminated point p = jB + K - 1, table row q = p + 1
             constexpr int k = decltype(K)::value;
             const int64_t q = (int64_t)j * B + k;
-            const cp<R> rhs = cn_rhs<MODE, R>(um1, u0, v[k], tab[3 * q + 1], tab[3 * q + 2]);
-            const cp<R> e = cn_elim<MODE, R>(rhs, dprev, tab[3 * q]);
+            const cp<R> rhs = cn_rhs<MODE, R>(um1, u0, v[k], row<CR>(tab, q, 1), row<CR>(tab, q, 2));
+            const cp<R> e = cn_elim<MODE, R>(rhs, dprev, row<CR>(tab, q, 0));
             d[U][k] = e;
             dprev = e;
             um1 = u0;
             u0 = v[k];
         });
+        if constexpr (kSums) {  // S_j with the constant c' (used only where every row is)
+            cp<R> sj = d[U][B - 1];
+            static_for<B - 1>([&](auto I) { sj = cn_back<MODE, R>(d[U][B - 2 - decltype(I)::value], rc, sj); });
+            bs[U] = sj;
+        }
         const int o = j - DW;
         if (o < o_lo || o >= o_hi) return;  // uniform
         const int64_t ob = (int64_t)o * B;
-        cp<R> x = {R(0), R(0)};
         cp<R> out[B];
-        // q = t + 1 from ob + (DW+1)B - 1 down to ob + 1; block (q - ob) / B of the
-        // window is slot (U + 1 + (q - ob) / B) mod (DW + 1).  Expanded as a fold
-        // so every slot index is a constant (a rolled loop would put d in scratch).
-        constexpr int L = (DW + 1) * B - 1;
-        static_for<L>([&](auto I) {
-            constexpr int i = L - decltype(I)::value;
-            x = cn_back<MODE, R>(d[(U + 1 + i / B) % (DW + 1)][i % B], tab[3 * (ob + i)], x);
-            if constexpr (i <= B) out[i - 1] = x;
-        });
+        if constexpr (CR && kSums) {
+            // x_{(o+1)B} = S_{o+1} + (-c')^B (S_{o+2} + ... (-c')^B S_j); block j - i is
+            // in slot (U + DW + 1 - i) mod (DW + 1)
+            cp<R> x = bs[U];
+            static_for<DW - 1>([&](auto I) {
+                constexpr int i = decltype(I)::value + 1;
+                x = kfma<MODE>(cB, x, bs[(U + DW + 1 - i) % (DW + 1)]);
+            });
+            out[B - 1] = x;
+            constexpr int so = (U + 1) % (DW + 1);  // block o
+            static_for<B - 1>([&](auto I) {
+                constexpr int k = B - 2 - decltype(I)::value;
+                x = cn_back<MODE, R>(d[so][k + 1], rc, x);
+                out[k] = x;
+            });
+        } else {
+            cp<R> x = {R(0), R(0)};
+            // q = t + 1 from ob + (DW+1)B - 1 down to ob + 1; block (q - ob) / B of the
+            // window is slot (U + 1 + (q - ob) / B) mod (DW + 1).  Expanded as a fold
+            // so every slot index is a constant (a rolled loop would put d in scratch).
+            constexpr int L = (DW + 1) * B - 1;
+            static_for<L>([&](auto I) {
+                constexpr int i = L - decltype(I)::value;
+                x = cn_back<MODE, R>(d[(U + 1 + i / B) % (DW + 1)][i % B], row<CR>(tab, ob + i, 0), x);
+                if constexpr (i <= B) out[i - 1] = x;
+            });
+        }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
             const int64_t t = ob + k;
@@ -227,6 +277,12 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
         Y.base = (int64_t)(w * kLanes + lane) + nx * ny * k;
         Y.stride = nx;
         Y.n = ny;
+        Y.rc = V{R(PY.c_inf[0]), R(PY.c_inf[1])};
+        Y.rb = V{R(PY.b_inf[0]), R(PY.b_inf[1])};
+        Y.rblo = V{R(PY.b_inf[2]), R(0)};
+        const cp<R> mc = {-Y.rc.x, -Y.rc.y};
+        Y.cB = mc;
+        for (int b = 1; b < B; ++b) Y.cB = cmul(Y.cB, mc);
     }
     const int j0 = Y.o_lo - DW > 0 ? Y.o_lo - DW : 0;
     const int j1 = Y.o_hi + DW;  // exclusive, uniform over the workgroup
@@ -283,8 +339,14 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
 #pragma unroll
             for (int r = 0; r < B; ++r) v[r] = from_v<R>(tile[j & 1][r][xy_slot<(int)sizeof(V)>(w * kLanes + lane)]);
             // one copy of the y step per window slot, so the slot index is a constant
+            const bool cr = YRegSolver<R, MODE, DW>::const_rows(j, PY.q_const, ny);
             static_for<DW + 1>([&](auto U) {
-                if (u == decltype(U)::value) Y.template process<decltype(U)::value>(v, j, taby, dst);
+                if (u == decltype(U)::value) {
+                    if (cr)
+                        Y.template process<decltype(U)::value, true>(v, j, taby, dst);
+                    else
+                        Y.template process<decltype(U)::value, false>(v, j, taby, dst);
+                }
             });
         }
         u = u == DW ? 0 : u + 1;
