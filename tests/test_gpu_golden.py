@@ -29,6 +29,10 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden")
 FP64_TOL, FP32_TOL = 1e-12, 1e-5
+# complex64 after each 2000-step phase: the level the bulk arithmetic reaches
+# (about 3e-7), well inside the 1e-5 target -- a reordering of the solver's sums
+# that biases the rounding shows up here first
+FP32_PHASE_END_TOL = 1e-6
 
 
 def say(msg):
@@ -89,6 +93,9 @@ def test_headline_2000_imag_then_2000_real_against_oracle(gp, prec):
             done = mark
             if mark >= 20:
                 check(plan.observables(psi), ref[key][str(mark)], fields, tol, f"{key} {mark}")
+        if prec == 1:
+            check(plan.observables(psi), ref[key][str(done)], ("norm", "mu", "energy"), FP32_PHASE_END_TOL,
+                  f"{key} {done} (phase end)")
     del psi
     torch.cuda.empty_cache()
 
