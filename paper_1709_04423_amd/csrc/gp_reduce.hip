@@ -41,13 +41,27 @@ __global__ __launch_bounds__(256) void k_scale(typename VT<R>::V *__restrict__ p
     }
 }
 
-// Sum of the per-workgroup norm partials of one step in a fixed order.
+// Sum of the per-workgroup norm partials of one step in a fixed order.  Each
+// thread adds its partials i = t, t + 256, ... in that order; they are loaded
+// eight at a time before the adds (a missing one as +0, which leaves the
+// non-negative sum unchanged), so the loads overlap instead of each one waiting
+// for the last: the same sums, bit for bit.
 __global__ __launch_bounds__(256) void k_norm_final(const double *__restrict__ part, int64_t np,
                                                     double *__restrict__ total)
 {
     __shared__ double lds[256 / kLanes];
+    constexpr int kBatch = 8;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+    for (int64_t i = threadIdx.x; i < np; i += kBatch * (int64_t)blockDim.x) {
+        double v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int64_t j = i + k * (int64_t)blockDim.x;
+            v[k] = j < np ? part[j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) acc += v[k];
+    }
     acc = wsum(acc);
     const int lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
     if (lane == 0) lds[wave] = acc;
