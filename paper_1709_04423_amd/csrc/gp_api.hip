@@ -123,7 +123,7 @@ constexpr int64_t kMinSweepWaves = 1024;  // one wavefront per SIMD of a 256-CU 
 
 static void choose_window(AxisPlan &A, gp_prec prec, int B, bool tile)
 {
-    const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -48);
+    const double tol = prec == GP_C128 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -44);
     int Kmin = 0;
     double bound = A.rho;
     while (bound > tol && Kmin < 100000) {

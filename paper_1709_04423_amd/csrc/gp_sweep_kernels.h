@@ -16,7 +16,7 @@
 // points past the block with u = 0: the neglected term is multiplied by
 // prod |c'| <= rho^(K+1) before it reaches an output.  K = D kBlock - 1 for a
 // compile-time D (1..4), the smallest with rho^(K+1) below 2^-60 (FP64) or
-// 2^-48 (FP32), so the back substitution is fully unrolled.  Rows past the end of
+// 2^-44 (FP32), so the back substitution is fully unrolled.  Rows past the end of
 // a line hold c' = 0, so the tail of every line is exact.  Each point is read
 // once and written once.  When the window does not fit in LDS, k_sweep_exact
 // runs the plain two-pass Thomas algorithm (eliminated values stored in

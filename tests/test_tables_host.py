@@ -157,7 +157,7 @@ def test_window_depth_and_exact_fallback():
     assert 0.019 < rho < 0.021 and rho ** (K + 1) <= 2.0 ** -60 and (K + 1) % 4 == 0
     assert rho ** (K + 1 - 4) > 2.0 ** -60
     _, _, K32, rho32 = binding.thomas_table(256, 0.05, 2e-4, binding.GP_REAL, binding.GP_C64)
-    assert rho32 ** (K32 + 1) <= 2.0 ** -48 and (K32 + 1) % 4 == 0 and K32 <= K
+    assert rho32 ** (K32 + 1) <= 2.0 ** -44 and (K32 + 1) % 4 == 0 and K32 <= K
     _, _, K2, rho2 = binding.thomas_table(256, 0.05, 1e-3, binding.GP_REAL, binding.GP_C128)
     assert K2 == 19 and rho2 ** 16 > 2.0 ** -60
     _, _, Kx, rho_x = binding.thomas_table(64, 0.05, 0.2, binding.GP_REAL, binding.GP_C128)
