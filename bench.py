@@ -307,6 +307,8 @@ def batch_leg(torch, binding, inputs, steps=1000):
                       [p.g for p in probs], binding.GP_C64)
     cache = os.path.join(tempfile.gettempdir(), f"sscn_batch_tune_{kernel_source_hash()}.txt")
     cfg = b.autotune(cache)
+    # lines per item and y segments as tuned per line length (x lines: nx, y lines: ny)
+    cfg["per_side"] = {str(n): b.side_config(n) for n in sorted({m for p in probs for m in p.n})}
     psis = [torch.from_numpy(inputs.gaussian(p.n, p.dx, p.omega).astype("complex64")).to("cuda") for p in probs]
     b.step(psis, 10)
     with Timer(torch) as t:

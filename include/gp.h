@@ -269,13 +269,16 @@ gp_status gp_batch_destroy(gp_batch *batch);
  * indices are left unchanged, so the caller must reload them. */
 gp_status gp_batch_step(gp_batch *batch, void *const *psis, int64_t nsteps, void *stream);
 
-/* Time candidate configurations -- persistent or phased launch, x lines per
- * work item (1, 2, 4), y segments per line (1..32, capped per problem by the
- * segments its y window allows), persistent grid size
- * (256..2048 workgroups) -- for 10 steps each on scratch copies of the problems
- * and keep the fastest.  cache_path (may be NULL): text file of previous
- * results, one line "key persistent lines ysegs grid" per batch shape (key: the
- * precision, mode and sorted problem sizes); read first, appended to.
+/* Time candidate configurations -- persistent or phased launch, lines per work
+ * item (1, 2, 4), y segments per line (1..32, capped per problem by the
+ * segments its y window allows), persistent grid size (256..2048 workgroups)
+ * -- for 10 steps each on scratch copies of the problems and keep the fastest;
+ * then, per line length (each side length of the problems, those carrying the
+ * most points first), try 1, 2, 4 and 8 lines per item and, for y lines solved
+ * by the windowed solver, 1..32 segments, keeping a change when it is at least
+ * 1% faster.  cache_path (may be NULL): text file of previous results, one line
+ * "key persistent lines ysegs grid [sides len:lines:ysegs ...]" per batch shape
+ * (key: the precision, mode and sorted problem sizes); read first, appended to.
  * Synchronises `stream`. */
 gp_status gp_batch_autotune(gp_batch *batch, const char *cache_path, void *stream);
 
@@ -288,9 +291,19 @@ gp_status gp_autotune(gp_batch *batch, const char *cache_path);
 gp_status gp_batch_set_wait_limit(gp_batch *batch, uint32_t polls);
 
 /* Read / set the configuration explicitly (persistent = 1 needs real time;
- * lines 1..64, ysegs 1..64, grid 1..65536; GP_EINVAL outside). */
+ * lines 1..64, ysegs 1..64, grid 1..65536; GP_EINVAL outside).  lines and
+ * ysegs are the defaults for every line length; setting them clears the
+ * per-length settings below. */
 gp_status gp_batch_get_config(const gp_batch *batch, int *persistent, int *lines, int *ysegs, int *grid);
 gp_status gp_batch_set_config(gp_batch *batch, int persistent, int lines, int ysegs, int grid);
+
+/* Per line length `side` (points on a line: a problem's nx for its x lines,
+ * its ny for its y lines): lines per work item and y segments (1..64 each)
+ * used instead of the defaults for the lines of that length.  get returns the
+ * values in effect for `side`.  GP_EINVAL for side < 1, a NULL pointer or
+ * values outside 1..64. */
+gp_status gp_batch_set_side_config(gp_batch *batch, int64_t side, int lines, int ysegs);
+gp_status gp_batch_get_side_config(const gp_batch *batch, int64_t side, int *lines, int *ysegs);
 
 /* Observables of problem k of a batch (as gp_observables).  GP_EINVAL for a
  * NULL batch or k outside 0..count-1. */

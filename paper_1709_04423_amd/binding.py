@@ -86,6 +86,8 @@ def lib():
             "gp_batch_get_config": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)],
             "gp_batch_set_config": [vp, i32, i32, i32, i32],
+            "gp_batch_set_side_config": [vp, i64, i32, i32],
+            "gp_batch_get_side_config": [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
             "gp_batch_set_wait_limit": [vp, ctypes.c_uint32],
             "gp_plan_timing_enable": [vp, i64],
             "gp_plan_timing_read": [vp, c_i64p, c_dp],
@@ -380,6 +382,15 @@ class Batch:
     def set_config(self, persistent=0, lines=4, ysegs=4, grid=1024):
         check(lib().gp_batch_set_config(self._h, int(persistent), int(lines), int(ysegs), int(grid)),
               "gp_batch_set_config")
+
+    def set_side_config(self, side, lines, ysegs):
+        check(lib().gp_batch_set_side_config(self._h, int(side), int(lines), int(ysegs)), "gp_batch_set_side_config")
+
+    def side_config(self, side):
+        v = [ctypes.c_int() for _ in range(2)]
+        check(lib().gp_batch_get_side_config(self._h, int(side), *[ctypes.byref(x) for x in v]),
+              "gp_batch_get_side_config")
+        return {"lines": v[0].value, "ysegs": v[1].value}
 
     def set_wait_limit(self, polls):
         check(lib().gp_batch_set_wait_limit(self._h, int(polls)), "gp_batch_set_wait_limit")

@@ -20,8 +20,9 @@
 //     queue drains without deadlock whatever the grid size.  Waits are bounded:
 //     past the limit the wavefront raises an error flag, every wavefront stops
 //     taking items, the launch ends, and gp_batch_step returns GP_ETIMEOUT.
-// The autotuner picks the run mode, lines per x item, y segments and the
-// persistent grid size by timing candidates on scratch copies.
+// The autotuner picks the run mode, lines per item, y segments and the
+// persistent grid size by timing candidates on scratch copies, then refines the
+// lines per item (and y segments) per line length: the problems' sides.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -61,10 +62,28 @@ inline bool batch_tiles(const AxisPlan &Y) { return Y.xq > 0 && Y.xq <= kBatchTi
 
 struct BatchConfig {
     int persistent = 0;  // 1: one launch for all steps (real time only)
-    int lines = 4;       // x lines per item
+    int lines = 4;       // lines per x item and per scan-solved y item
     int ysegs = 4;       // y segments per line (capped per problem)
     int grid = 1024;     // workgroups of the persistent launch
     unsigned spin_limit = kSpinLimit;  // polls before a dependency wait gives up
+    // per line length (a problem's side): lines per item and y segments that
+    // replace the two above for the lines of that length
+    std::map<int64_t, int> side_lines, side_ysegs;
+    int lines_for(int64_t len) const
+    {
+        const auto it = side_lines.find(len);
+        return it == side_lines.end() ? lines : it->second;
+    }
+    int ysegs_for(int64_t len) const
+    {
+        const auto it = side_ysegs.find(len);
+        return it == side_ysegs.end() ? ysegs : it->second;
+    }
+    // the settings that shape the item lists
+    bool same_items(const BatchConfig &o) const
+    {
+        return lines == o.lines && ysegs == o.ysegs && side_lines == o.side_lines && side_ysegs == o.side_ysegs;
+    }
 };
 
 }  // namespace gp
@@ -88,7 +107,7 @@ struct gp_batch {
     int qmax_y = 0;                // largest y points per lane of the scan-solved y lines (0: none)
     int smax = 6;                  // most scan steps of any scan-solved line: 3 or 6 (sizes the solvers' registers)
     std::vector<const void *> bound; // psi pointers the device parameters were built for
-    int bound_cfg_lines = -1, bound_cfg_ysegs = -1;
+    gp::BatchConfig bound_cfg;       // and the configuration they were built for
 };
 
 namespace gp {
@@ -374,8 +393,7 @@ static int y_segments(const gp_plan *p, int want)
 // (Re)build the device parameters and item lists for psis and the current config.
 static gp_status prepare(gp_batch *b, void *const *psis)
 {
-    bool same = (int)b->bound.size() == b->count && b->bound_cfg_lines == b->cfg.lines &&
-                b->bound_cfg_ysegs == b->cfg.ysegs;
+    bool same = (int)b->bound.size() == b->count && b->bound_cfg.same_items(b->cfg);
     for (int k = 0; same && k < b->count; ++k) same = b->bound[k] == psis[k];
     if (same) return GP_OK;
     free_batch_device(b);
@@ -400,12 +418,12 @@ static gp_status prepare(gp_batch *b, void *const *psis)
         py[k].norm_total = norm_total(p, 0);
         py[k].norm_out = norm_partials(p, 0);
         const int64_t ny = p->n[1], nx = p->n[0];
-        for (int64_t l = 0; l < ny; l += b->cfg.lines)
-            xk[k].push_back({k, 0, 1, (int)std::min<int64_t>(b->cfg.lines, ny - l), l});
+        const int lx = b->cfg.lines_for(nx);
+        for (int64_t l = 0; l < ny; l += lx) xk[k].push_back({k, 0, 1, (int)std::min<int64_t>(lx, ny - l), l});
         nx_per[k] = (int)xk[k].size();
         if (batch_tiles(p->ax[1])) {  // scan-solved y lines: items of whole tiles, one norm partial each
             const int64_t tl = b->prec == GP_C128 ? col_tile_lines<double>() : col_tile_lines<float>();
-            int64_t per = std::max<int64_t>(b->cfg.lines, (nx + p->n_norm - 1) / p->n_norm);
+            int64_t per = std::max<int64_t>(b->cfg.lines_for(ny), (nx + p->n_norm - 1) / p->n_norm);
             per = (per + tl - 1) / tl * tl;
             for (int64_t l = 0; l < nx; l += per) {
                 const int slot = (int)yk[k].size();
@@ -414,7 +432,7 @@ static gp_status prepare(gp_batch *b, void *const *psis)
             nparts[k] = (int64_t)yk[k].size();
             lds_wave = std::max(lds_wave, lds_tile(p->ax[1].xq));
         } else {
-            const int segs = y_segments(p, b->cfg.ysegs);
+            const int segs = y_segments(p, b->cfg.ysegs_for(ny));
             const int64_t groups = (nx + kLanes - 1) / kLanes;
             for (int s = 0; s < segs; ++s)
                 for (int64_t g = 0; g < groups; ++g) yk[k].push_back({k, s, segs, 0, g});
@@ -449,8 +467,7 @@ static gp_status prepare(gp_batch *b, void *const *psis)
     b->nyi = (int64_t)yi.size();
     b->lds_wave = lds_wave;
     b->bound.assign(psis, psis + b->count);
-    b->bound_cfg_lines = b->cfg.lines;
-    b->bound_cfg_ysegs = b->cfg.ysegs;
+    b->bound_cfg = b->cfg;
     return GP_OK;
 }
 
@@ -700,10 +717,27 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
             std::string k2;
             BatchConfig c;
             c.spin_limit = b->cfg.spin_limit;
-            if (is >> k2 >> c.persistent >> c.lines >> c.ysegs >> c.grid && k2 == key) {
-                b->cfg = c;
-                return GP_OK;
+            if (!(is >> k2 >> c.persistent >> c.lines >> c.ysegs >> c.grid) || k2 != key) continue;
+            // optional per-side settings: "sides" then "len:lines:ysegs" triples
+            std::string tok;
+            bool ok = true;
+            if (is >> tok) {
+                ok = tok == "sides";
+                while (ok && is >> tok) {
+                    long long len = 0;
+                    int ln = 0, ys = 0;
+                    ok = std::sscanf(tok.c_str(), "%lld:%d:%d", &len, &ln, &ys) == 3 && len > 0 && ln >= 1 &&
+                         ln <= 64 && ys >= 1 && ys <= 64;
+                    if (ok) {
+                        c.side_lines[len] = ln;
+                        c.side_ysegs[len] = ys;
+                    }
+                }
             }
+            if (!ok) continue;
+            b->cfg = c;
+            b->bound.clear();
+            return GP_OK;
         }
     }
     // scratch copies of every problem (Gaussian-like content does not matter for timing)
@@ -718,6 +752,31 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
             return hip_fail(e, "autotune scratch");
         }
     }
+    const BatchConfig saved = b->cfg;
+    std::vector<int64_t> saved_steps;
+    for (gp_plan *p : b->plans) saved_steps.push_back(p->step);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    gp_status st = GP_OK;
+    const int64_t steps = 10;
+    // ms for `steps` steps under config c (+inf when it cannot run)
+    auto time_cfg = [&](const BatchConfig &c) -> float {
+        b->cfg = c;
+        st = prepare(b, scratch.data());
+        if (st != GP_OK) return 1e30f;
+        if (run_batch(b, 0, 2, s) != hipSuccess) return 1e30f;  // warm-up
+        hipEventRecord(e0, s);
+        const hipError_t er = run_batch(b, 0, steps, s);
+        hipEventRecord(e1, s);
+        if (er != hipSuccess) return 1e30f;
+        hipEventSynchronize(e1);
+        if (check_error_flag(b, s) != GP_OK) return 1e30f;
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    // 1. one setting for every problem
     std::vector<BatchConfig> cands;
     for (int lines : {1, 2, 4})
         for (int ysegs : {1, 2, 4, 8, 16, 32}) {
@@ -734,33 +793,57 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
                     cands.push_back(c);
                 }
         }
-    const BatchConfig saved = b->cfg;
-    std::vector<int64_t> saved_steps;
-    for (gp_plan *p : b->plans) saved_steps.push_back(p->step);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
     float best = 1e30f;
     BatchConfig best_cfg = saved;
-    gp_status st = GP_OK;
-    const int64_t steps = 10;
     for (const BatchConfig &c : cands) {
-        b->cfg = c;
-        st = prepare(b, scratch.data());
+        const float ms = time_cfg(c);
         if (st != GP_OK) break;
-        if (run_batch(b, 0, 2, s) != hipSuccess) continue;  // warm-up
-        hipEventRecord(e0, s);
-        e = run_batch(b, 0, steps, s);
-        hipEventRecord(e1, s);
-        if (e != hipSuccess) continue;
-        hipEventSynchronize(e1);
-        if (check_error_flag(b, s) != GP_OK) continue;
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
             best = ms;
             best_cfg = c;
         }
+    }
+    // 2. per line length, largest total first: lines per item (x lines and
+    // scan-solved y lines of that length) and y segments (windowed y lines),
+    // kept when at least 1% faster
+    if (st == GP_OK && best < 1e29f) {
+        std::map<int64_t, int64_t> pts_x, pts_yw;  // points on lines of each length
+        for (const gp_plan *p : b->plans) {
+            pts_x[p->n[0]] += p->npts;
+            if (batch_tiles(p->ax[1]))
+                pts_x[p->n[1]] += p->npts;
+            else
+                pts_yw[p->n[1]] += p->npts;
+        }
+        auto by_size = [](const std::map<int64_t, int64_t> &m) {
+            std::vector<std::pair<int64_t, int64_t>> v(m.begin(), m.end());
+            std::sort(v.begin(), v.end(), [](const auto &a, const auto &c) { return a.second > c.second; });
+            return v;
+        };
+        for (const auto &[len, pts] : by_size(pts_x))
+            for (int lines : {1, 2, 4, 8}) {
+                if (st != GP_OK || lines == best_cfg.lines_for(len)) continue;
+                BatchConfig c = best_cfg;
+                c.side_lines[len] = lines;
+                const float ms = time_cfg(c);
+                if (st != GP_OK) break;
+                if (ms < 0.99f * best) {
+                    best = ms;
+                    best_cfg = c;
+                }
+            }
+        for (const auto &[len, pts] : by_size(pts_yw))
+            for (int ysegs : {1, 2, 4, 8, 16, 32}) {
+                if (st != GP_OK || ysegs == best_cfg.ysegs_for(len)) continue;
+                BatchConfig c = best_cfg;
+                c.side_ysegs[len] = ysegs;
+                const float ms = time_cfg(c);
+                if (st != GP_OK) break;
+                if (ms < 0.99f * best) {
+                    best = ms;
+                    best_cfg = c;
+                }
+            }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -771,8 +854,16 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
     if (st != GP_OK) return st;
     if (cache_path) {
         std::ofstream o(cache_path, std::ios::app);
-        o << key << " " << b->cfg.persistent << " " << b->cfg.lines << " " << b->cfg.ysegs << " " << b->cfg.grid
-          << "\n";
+        o << key << " " << b->cfg.persistent << " " << b->cfg.lines << " " << b->cfg.ysegs << " " << b->cfg.grid;
+        std::map<int64_t, int> sides;
+        for (const auto &kv : b->cfg.side_lines) sides[kv.first] = 1;
+        for (const auto &kv : b->cfg.side_ysegs) sides[kv.first] = 1;
+        if (!sides.empty()) {
+            o << " sides";
+            for (const auto &kv : sides)
+                o << " " << kv.first << ":" << b->cfg.lines_for(kv.first) << ":" << b->cfg.ysegs_for(kv.first);
+        }
+        o << "\n";
     }
     return GP_OK;
 }
@@ -806,7 +897,27 @@ gp_status gp_batch_set_config(gp_batch *b, int persistent, int lines, int ysegs,
     b->cfg.lines = lines;
     b->cfg.ysegs = ysegs;
     b->cfg.grid = grid;
+    b->cfg.side_lines.clear();
+    b->cfg.side_ysegs.clear();
     b->bound.clear();
+    return GP_OK;
+}
+
+gp_status gp_batch_set_side_config(gp_batch *b, int64_t side, int lines, int ysegs)
+{
+    if (!b || side < 1 || lines < 1 || lines > 64 || ysegs < 1 || ysegs > 64)
+        return set_error("bad argument"), GP_EINVAL;
+    b->cfg.side_lines[side] = lines;
+    b->cfg.side_ysegs[side] = ysegs;
+    b->bound.clear();
+    return GP_OK;
+}
+
+gp_status gp_batch_get_side_config(const gp_batch *b, int64_t side, int *lines, int *ysegs)
+{
+    if (!b || side < 1 || !lines || !ysegs) return set_error("bad argument"), GP_EINVAL;
+    *lines = b->cfg.lines_for(side);
+    *ysegs = b->cfg.ysegs_for(side);
     return GP_OK;
 }
 

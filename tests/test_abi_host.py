@@ -97,6 +97,9 @@ def test_null_handles_are_rejected():
     assert L.gp_step_record(None, None, 1, None, None) == binding.GP_EINVAL
     assert L.gp_plan_set_xy_fusion(None, 1) == binding.GP_EINVAL
     assert L.gp_batch_set_config(None, 0, 1, 1, 1) == binding.GP_EINVAL
+    iv = ctypes.c_int()
+    assert L.gp_batch_set_side_config(None, 128, 1, 1) == binding.GP_EINVAL
+    assert L.gp_batch_get_side_config(None, 128, ctypes.byref(iv), ctypes.byref(iv)) == binding.GP_EINVAL
     assert L.gp_plan_timing_enable(None, 4) == binding.GP_EINVAL
     assert L.gp_copy_probe(None, None, 16, None) == binding.GP_EINVAL
     assert L.gp_plan_destroy(None) == binding.GP_OK

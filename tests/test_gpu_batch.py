@@ -134,5 +134,33 @@ def test_autotune_and_cache(gp, tmp_path):
     b2 = gp.Batch(sizes, 0.05, 1e-3, 1, [(1.0, 1.2)] * 12, [100.0] * 12, gp.GP_C64)
     assert b2.autotune(cache) == cfg  # read back without timing
     assert open(cache).read().count("\n") == 1
+    sides = sorted({n for s in sizes for n in s})
+    assert [b2.side_config(n) for n in sides] == [b.side_config(n) for n in sides]  # per-length settings too
+    say(f"per side {[(n, b.side_config(n)) for n in sides]}")
     psis = [torch.zeros(s[::-1], dtype=torch.complex64, device="cuda") for s in sizes]
     b.step(psis, 3)
+
+
+def test_per_side_settings_change_grouping_not_results(gp):
+    # real time: every scan-solved line is solved alone, so regrouping lines
+    # into items leaves the bits unchanged; other y segments of a windowed line
+    # move its results only within the window bound
+    _, ref = run_batch(gp, 1, gp.GP_C64, dict(persistent=0, lines=2, ysegs=4))
+    dtype = np.complex64
+    b = gp.Batch(SIZES, DX, DT, 1, OMEGA, G, gp.GP_C64)
+    b.set_config(persistent=0, lines=2, ysegs=4)
+    b.set_side_config(128, 8, 1)   # x lines of problem 0 and y lines of problem 2
+    b.set_side_config(600, 1, 16)  # the windowed y lines of problem 6
+    assert b.side_config(128) == {"lines": 8, "ysegs": 1}
+    assert b.side_config(96) == {"lines": 2, "ysegs": 4}  # the defaults
+    psis = [initial(k, dtype) for k in range(len(SIZES))]
+    b.step(psis, 7)
+    for k in range(len(SIZES)):
+        got = psis[k].cpu().numpy()
+        assert np.array_equal(got, ref[k]) if SIZES[k][1] <= 512 else max_rel(got, ref[k]) <= 1e-6, k
+    b.set_config(persistent=0, lines=4, ysegs=2)  # clears the per-length settings
+    assert b.side_config(128) == {"lines": 4, "ysegs": 2}
+    with pytest.raises(gp.GpError):
+        b.set_side_config(0, 1, 1)
+    with pytest.raises(gp.GpError):
+        b.set_side_config(128, 65, 1)
