@@ -759,6 +759,13 @@ static gp_status cartesian_steps(gp_plan *p, void *psi, int64_t nsteps, void *st
     const bool fused = p->ndim == 3 && p->xy_segs > 0 && p->xy_enabled;
     const size_t bytes = (size_t)p->npts * elem_bytes(p->prec);
     hipError_t e;
+    if (p->ndim == 1 && !states && p->sched.empty() && p->ax[0].xq > 0 && p->ax[0].xq <= k1DMaxQ) {
+        // one line: the whole run in one launch
+        timing_begin(p, K_SWEEP_X, s);
+        e = launch_steps_1d(p, psi, nsteps, norm_total(p, p->step + nsteps - 1), s);
+        timing_end(p, s);
+        return e == hipSuccess ? GP_OK : hip_fail(e, "1D steps launch");
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         const int64_t n = p->step + k;
         void *copy_to = states ? (char *)states + (size_t)k * bytes : nullptr;

@@ -194,6 +194,10 @@ hipError_t launch_norm_final(gp_plan *p, int64_t step_index, hipStream_t s);
 inline double *norm_partials(gp_plan *p, int64_t step) { return p->d_norm + (step & 1) * p->n_norm; }
 inline double *norm_total(gp_plan *p, int64_t step) { return p->d_norm + 2 * p->n_norm + (step & 1); }
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s);
+// nsteps 1D steps from step p->step in one launch (one wavefront; x points per
+// lane 1..8, static trap); *total_out gets the last step's norm total.
+constexpr int k1DMaxQ = 8;
+hipError_t launch_steps_1d(const gp_plan *p, void *psi, int64_t nsteps, double *total_out, hipStream_t s);
 // Strided axis solved with the scan solver (AxisPlan::xq > 0 on an axis other
 // than 0): flags 0 or F_NORM_OUT.
 hipError_t launch_col_scan(const gp_plan *p, int axis, const SweepParams &P, int flags, const void *tab,

@@ -217,6 +217,82 @@ hipError_t launch_col_scan(const gp_plan *p, int axis, const SweepParams &P, int
                               : launch_col_mode<float, GP_REAL>(P, flags, Q, tab, s);
 }
 
+// A 1D run in one launch.  A 1D grid is one line, solved by one wavefront, so
+// consecutive steps need no ordering across workgroups: the wavefront runs them
+// in turn, each exactly as the x sweep kernel would (the same routine and
+// flags: potential substep on load, deferred renormalisation in imaginary
+// time), and keeps the imaginary-time norm total in LDS, where the separate
+// launches pass it through the norm kernel.  The total is the same sum as the
+// separate kernels form (their extra terms are zeros), so the results are too.
+// Each lane reloads only the points it stored itself.  *total_out receives the
+// last step's norm total (the scale applied after the call).
+template <typename R, int MODE, int Q, int SMAX>
+__global__ __launch_bounds__(kLanes) void k_steps_1d(SweepParams P, typename CT<R>::V *psi,
+                                                     const typename CT<R>::V *__restrict__ tab, int64_t nsteps,
+                                                     double *total_out)
+{
+    using V = typename CT<R>::V;
+    constexpr bool kImag = MODE == GP_IMAG;
+    constexpr int kFlags = F_FUSE_N | (kImag ? F_NORM_OUT : 0);
+    const int lane = threadIdx.x & (kLanes - 1);
+    __shared__ V xl[kLanes * (Q + 1)];
+    __shared__ double tot;
+    SweepParams Pr = P;  // renormalising steps read the previous step's total from LDS
+    Pr.norm_total = &tot;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        double nacc = 0.0, acc_w = 0.0, acc_g = 0.0;
+        if (kImag && k > 0)
+            x_scan_wave<R, MODE, kFlags | F_RENORM, Q, SMAX>(Pr, psi, psi, tab, nullptr, 0, 1, nacc, acc_w, acc_g, xl);
+        else
+            x_scan_wave<R, MODE, kFlags, Q, SMAX>(P, psi, psi, tab, nullptr, 0, 1, nacc, acc_w, acc_g, xl);
+        if constexpr (kImag) {
+            nacc = wave_sum(nacc);
+            __syncthreads();  // every lane has read the previous total
+            if (lane == 0) tot = nacc;
+            __syncthreads();
+        }
+    }
+    if (kImag && lane == 0 && nsteps > 0) *total_out = tot;
+}
+
+template <typename R, int MODE, int Q>
+static hipError_t launch_steps_1d_q(const SweepParams &P, void *psi, int64_t nsteps, double *total_out,
+                                    hipStream_t s)
+{
+    using V = typename CT<R>::V;
+    if (P.scan_steps <= 3)
+        hipLaunchKernelGGL((k_steps_1d<R, MODE, Q, 3>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, (const V *)P.tab,
+                           nsteps, total_out);
+    else
+        hipLaunchKernelGGL((k_steps_1d<R, MODE, Q, 6>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, (const V *)P.tab,
+                           nsteps, total_out);
+    return hipGetLastError();
+}
+
+template <typename R, int MODE>
+static hipError_t launch_steps_1d_mode(const SweepParams &P, int Q, void *psi, int64_t nsteps, double *total_out,
+                                       hipStream_t s)
+{
+    switch (Q) {
+    case 1: return launch_steps_1d_q<R, MODE, 1>(P, psi, nsteps, total_out, s);
+    case 2: return launch_steps_1d_q<R, MODE, 2>(P, psi, nsteps, total_out, s);
+    case 4: return launch_steps_1d_q<R, MODE, 4>(P, psi, nsteps, total_out, s);
+    case 8: return launch_steps_1d_q<R, MODE, 8>(P, psi, nsteps, total_out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_steps_1d(const gp_plan *p, void *psi, int64_t nsteps, double *total_out, hipStream_t s)
+{
+    const SweepParams P = make_sweep_params(p, 0, psi, psi, false, p->step, nullptr);
+    const int Q = p->ax[0].xq;
+    if (p->prec == GP_C128)
+        return p->mode == GP_IMAG ? launch_steps_1d_mode<double, GP_IMAG>(P, Q, psi, nsteps, total_out, s)
+                                  : launch_steps_1d_mode<double, GP_REAL>(P, Q, psi, nsteps, total_out, s);
+    return p->mode == GP_IMAG ? launch_steps_1d_mode<float, GP_IMAG>(P, Q, psi, nsteps, total_out, s)
+                              : launch_steps_1d_mode<float, GP_REAL>(P, Q, psi, nsteps, total_out, s);
+}
+
 hipError_t launch_x_scan(const gp_plan *p, const SweepParams &P, int flags, const void *tab, hipStream_t s)
 {
     const int Q = p->ax[0].xq;
