@@ -44,14 +44,14 @@ void timing_begin(gp_plan *p, int kind, hipStream_t s)
     Timing &T = p->timing;
     if (T.capacity == 0 || T.used >= T.capacity) return;
     T.kind[T.used] = kind;
-    hipEventRecord(T.ev[2 * T.used], s);
+    (void)hipEventRecord(T.ev[2 * T.used], s);  // instrumentation only
 }
 
 void timing_end(gp_plan *p, hipStream_t s)
 {
     Timing &T = p->timing;
     if (T.capacity == 0 || T.used >= T.capacity) return;
-    hipEventRecord(T.ev[2 * T.used + 1], s);
+    (void)hipEventRecord(T.ev[2 * T.used + 1], s);
     ++T.used;
 }
 
@@ -377,19 +377,19 @@ static void free_plan(gp_plan *p)
 {
     if (!p) return;
     for (int a = 0; a < 3; ++a) {
-        if (p->ax[a].d_rtab) hipFree(p->ax[a].d_rtab);
-        if (p->ax[a].d_rmul) hipFree(p->ax[a].d_rmul);
-        if (p->ax[a].d_tab) hipFree(p->ax[a].d_tab);
-        if (p->ax[a].d_tab_adj) hipFree(p->ax[a].d_tab_adj);
-        if (p->ax[a].d_xmul) hipFree(p->ax[a].d_xmul);
-        if (p->ax[a].d_xmul_adj) hipFree(p->ax[a].d_xmul_adj);
+        if (p->ax[a].d_rtab) (void)hipFree(p->ax[a].d_rtab);
+        if (p->ax[a].d_rmul) (void)hipFree(p->ax[a].d_rmul);
+        if (p->ax[a].d_tab) (void)hipFree(p->ax[a].d_tab);
+        if (p->ax[a].d_tab_adj) (void)hipFree(p->ax[a].d_tab_adj);
+        if (p->ax[a].d_xmul) (void)hipFree(p->ax[a].d_xmul);
+        if (p->ax[a].d_xmul_adj) (void)hipFree(p->ax[a].d_xmul_adj);
     }
-    if (p->d_work) hipFree(p->d_work);
-    if (p->d_norm) hipFree(p->d_norm);
-    if (p->d_adj) hipFree(p->d_adj);
-    if (p->d_adj_done) hipFree(p->d_adj_done);
-    if (p->d_obs) hipFree(p->d_obs);
-    for (hipEvent_t e : p->timing.ev) hipEventDestroy(e);
+    if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_norm) (void)hipFree(p->d_norm);
+    if (p->d_adj) (void)hipFree(p->d_adj);
+    if (p->d_adj_done) (void)hipFree(p->d_adj_done);
+    if (p->d_obs) (void)hipFree(p->d_obs);
+    for (hipEvent_t e : p->timing.ev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -939,7 +939,7 @@ gp_status gp_plan_timing_enable(gp_plan *p, int64_t capacity)
 {
     if (!p || capacity < 0) return set_error("bad argument"), GP_EINVAL;
     Timing &T = p->timing;
-    for (hipEvent_t ev : T.ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : T.ev) (void)hipEventDestroy(ev);
     T.ev.clear();
     T.kind.clear();
     T.used = 0;

@@ -357,14 +357,14 @@ __global__ __launch_bounds__(kLanes *kBatchWaves) void k_batch_persistent(
 
 static void free_batch_device(gp_batch *b)
 {
-    hipFree(b->d_px);
-    hipFree(b->d_py);
-    hipFree(b->d_xi);
-    hipFree(b->d_yi);
-    hipFree(b->d_ctr);
-    hipFree(b->d_nx_per);
-    hipFree(b->d_ny_per);
-    hipFree(b->d_nparts);
+    (void)hipFree(b->d_px);
+    (void)hipFree(b->d_py);
+    (void)hipFree(b->d_xi);
+    (void)hipFree(b->d_yi);
+    (void)hipFree(b->d_ctr);
+    (void)hipFree(b->d_nx_per);
+    (void)hipFree(b->d_ny_per);
+    (void)hipFree(b->d_nparts);
     b->d_px = b->d_py = nullptr;
     b->d_xi = b->d_yi = nullptr;
     b->d_ctr = b->d_nx_per = b->d_ny_per = nullptr;
@@ -748,16 +748,21 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
         e = hipMalloc(&scratch[k], bytes);
         if (e == hipSuccess) e = hipMemsetAsync(scratch[k], 0, bytes, s);
         if (e != hipSuccess) {
-            for (void *q : scratch) hipFree(q);
+            for (void *q : scratch) (void)hipFree(q);
             return hip_fail(e, "autotune scratch");
         }
     }
     const BatchConfig saved = b->cfg;
     std::vector<int64_t> saved_steps;
     for (gp_plan *p : b->plans) saved_steps.push_back(p->step);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        for (void *q : scratch) (void)hipFree(q);
+        return hip_fail(e, "autotune events");
+    }
     gp_status st = GP_OK;
     const int64_t steps = 10;
     // ms for `steps` steps under config c (+inf when it cannot run)
@@ -766,14 +771,13 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
         st = prepare(b, scratch.data());
         if (st != GP_OK) return 1e30f;
         if (run_batch(b, 0, 2, s) != hipSuccess) return 1e30f;  // warm-up
-        hipEventRecord(e0, s);
+        if (hipEventRecord(e0, s) != hipSuccess) return 1e30f;
         const hipError_t er = run_batch(b, 0, steps, s);
-        hipEventRecord(e1, s);
-        if (er != hipSuccess) return 1e30f;
-        hipEventSynchronize(e1);
+        if (hipEventRecord(e1, s) != hipSuccess || er != hipSuccess) return 1e30f;
+        if (hipEventSynchronize(e1) != hipSuccess) return 1e30f;
         if (check_error_flag(b, s) != GP_OK) return 1e30f;
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30f;
         return ms;
     };
     // 1. one setting for every problem
@@ -845,9 +849,9 @@ gp_status gp_batch_autotune(gp_batch *b, const char *cache_path, void *stream)
                 }
             }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    for (void *q : scratch) hipFree(q);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (void *q : scratch) (void)hipFree(q);
     for (int k = 0; k < b->count; ++k) b->plans[k]->step = saved_steps[k];
     b->cfg = st == GP_OK ? best_cfg : saved;
     b->bound.clear();  // rebuild for the caller's grids on the next step
