@@ -316,11 +316,17 @@ def batch_leg(torch, binding, inputs, steps=1000):
     pts = sum(p.points for p in probs)
     v = pts * steps / (t.ms * 1e-3)
     log(f"batch: {v:.3e} point-updates/s ({t.ms / steps:.3f} ms/step, config {cfg})")
-    return {"value": v, "unit": "grid-point updates/s", "problems": len(probs), "points": pts, "steps": steps,
-            "ms_per_step": t.ms / steps, "dtype": "c64 bulk, f64 reductions", "config": cfg,
-            "hbm_frac_at_32B": 32 * v / 1e9 / HBM_PEAK_GBPS,
-            "note": "2D: 32 B per point-step (one complex64 read and write per sweep, two sweeps); "
-                    "the 44 MB working set stays in the L2/MALL caches"}
+    out = {"value": v, "unit": "grid-point updates/s", "problems": len(probs), "points": pts, "steps": steps,
+           "ms_per_step": t.ms / steps, "dtype": "c64 bulk, f64 reductions", "config": cfg,
+           "hbm_frac_at_32B": 32 * v / 1e9 / HBM_PEAK_GBPS,
+           "note": "2D: 32 B per point-step (one complex64 read and write per sweep, two sweeps)"}
+    # bytes through the L2 (FETCH_SIZE / WRITE_SIZE counters) of one step's two launches,
+    # measured for the tuned configuration the profile recorded
+    dram = read_traffic_summary(os.path.join(ROOT, "profiles", "traffic_batch_form_c64.md"))
+    if dram and dram.get("kernel_source_hash") == kernel_source_hash() and dram.get("bytes_per_step"):
+        out["dram_bytes_per_step"] = dram["bytes_per_step"]
+        out["dram_GBps"] = dram["bytes_per_step"] / (t.ms / steps * 1e-3) / 1e9
+    return out
 
 
 def adjoint_leg(torch, binding, inputs):
