@@ -64,6 +64,9 @@ CASES_FP64 = [
     ((512,), (0.05,), 5e-4, (1.0,), 62.74, 40),
     ((37,), (0.2,), 1e-2, (1.0,), 5.0, 3),
     ((1,), (0.2,), 1e-2, (1.0,), 5.0, 2),
+    # 1D lines of 2 and 4 points per lane (a whole 1D run is one launch)
+    ((100,), (0.1,), 1e-3, (1.0,), 20.0, 5),
+    ((200,), (0.08,), 1e-3, (1.0,), 40.0, 4),
     ((70, 45), (0.1, 0.12), 1e-3, (1.0, 1.5), 30.0, 3),
     ((33, 130), (0.1, 0.05), 2e-3, (1.0, 0.7), 100.0, 2),
     ((64, 64), (0.1, 0.1), 1e-3, (1.0, 1.0), 200.0, 5),
@@ -163,6 +166,27 @@ def test_steps_split_across_calls_equal_one_call(gp):
             # imaginary time renormalises at the end of each call: rounding differs
             assert max_rel(ga, gb) <= FP64_TOL
         assert a.info()["step"] == 6 and b.info()["step"] == 6
+
+
+def test_1d_steps_split_across_calls_equal_one_call(gp):
+    # a 1D call runs all its steps in one launch: splitting the call changes
+    # nothing in real time, and only the end-of-call renormalisation's rounding
+    # in imaginary time
+    n, dx, dt, omega, g = (300,), (0.06,), 1e-3, (1.0,), 30.0
+    psi0 = inputs.gaussian(n, dx, omega) + 0.05 * inputs.random_field(n, 9)
+    for mode in (0, 1):
+        a = gp.Plan(n, dx, dt, mode, omega, g)
+        b = gp.Plan(n, dx, dt, mode, omega, g)
+        pa, pb = to_dev(psi0), to_dev(psi0)
+        a.step(pa, 12)
+        for _ in range(4):
+            b.step(pb, 3)
+        ga, gb = pa.cpu().numpy(), pb.cpu().numpy()
+        if mode == 1:
+            assert np.array_equal(ga, gb)
+        else:
+            assert max_rel(ga, gb) <= FP64_TOL
+        assert a.info()["step"] == 12 and b.info()["step"] == 12
 
 
 def test_zero_steps_is_a_no_op(gp):
