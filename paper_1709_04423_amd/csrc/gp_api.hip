@@ -808,6 +808,16 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t nsteps, void *stream)
     hipError_t e = hipSetDevice(p->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const bool imag = p->mode == GP_IMAG;
+    if (p->geom != GP_CARTESIAN && p->ndim == 1 && p->sched.empty()) {  // one radial line: one launch
+        e = launch_radial_steps(p, psi, nsteps, norm_total(p, p->step + nsteps - 1), s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric-trap steps launch");
+        p->step += nsteps;
+        if (imag) {
+            e = launch_scale(p, psi, s);
+            if (e != hipSuccess) return hip_fail(e, "scale launch");
+        }
+        return GP_OK;
+    }
     if (p->geom != GP_CARTESIAN) {  // symmetric trap: radial line solver, then z (axial)
         for (int64_t k = 0; k < nsteps; ++k) {
             const int64_t n = p->step + k;

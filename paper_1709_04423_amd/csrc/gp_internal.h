@@ -236,6 +236,9 @@ int64_t radial_line_groups(const gp_plan *p);
 int64_t radial_norm_groups(const gp_plan *p);
 hipError_t launch_radial_line(gp_plan *p, const void *src, void *dst, int flags, int64_t step_index, hipStream_t s);
 hipError_t launch_radial_norm(gp_plan *p, const void *psi, int64_t step_index, hipStream_t s);
+// nsteps steps of a circular or spherical plan (one radial line) from p->step in
+// one launch; *total_out gets the last step's norm total.
+hipError_t launch_radial_steps(gp_plan *p, void *psi, int64_t nsteps, double *total_out, hipStream_t s);
 hipError_t launch_radial_obs(gp_plan *p, const void *psi, double *part, int64_t nb, hipStream_t s);
 
 // Window choice of one axis exactly as gp_plan_create makes it (host only, no

@@ -37,20 +37,18 @@ __device__ __forceinline__ double radial_weight(int64_t i, double dr, int d)
     return d == 3 ? r * r + dr * dr / 12.0 : r;
 }
 
+// One wavefront solves radial line `line` (src -> dst), adding the weighted
+// norm of its output to nacc when FLAGS has F_NORM_OUT.
 template <typename R, int MODE, int FLAGS, int Q>
-__global__ __launch_bounds__(kLanes *kRWaves) void k_radial_line(SweepParams P, const typename CT<R>::V *src,
-                                                                 typename CT<R>::V *dst,
-                                                                 const typename CT<R>::V *__restrict__ rows,
-                                                                 const typename CT<R>::V *__restrict__ rmul)
+__device__ __forceinline__ void radial_line_wave(const SweepParams &P, const typename CT<R>::V *src,
+                                                 typename CT<R>::V *dst, const typename CT<R>::V *__restrict__ rows,
+                                                 const typename CT<R>::V *__restrict__ rmul, int64_t line, int lane,
+                                                 double &nacc)
 {
     using V = typename CT<R>::V;
-    const int lane = threadIdx.x & (kLanes - 1);
-    const int wave = threadIdx.x / kLanes;
-    const int64_t line = (int64_t)blockIdx.x * kRWaves + wave;
     const int64_t n = P.n;
     const cp<R> zero = {R(0), R(0)};
-    double nacc = 0.0;
-    if (line < P.nlines) {  // uniform across the wavefront
+    {
         const int64_t base = line * n;
         LineCtx<R> L = line_ctx_of<R>(P, line);
         if (FLAGS & F_RENORM) L.scale = 1.0 / sqrt(P.dV * P.norm_total[0]);
@@ -123,6 +121,20 @@ __global__ __launch_bounds__(kLanes *kRWaves) void k_radial_line(SweepParams P, 
             }
         }
     }
+}
+
+template <typename R, int MODE, int FLAGS, int Q>
+__global__ __launch_bounds__(kLanes *kRWaves) void k_radial_line(SweepParams P, const typename CT<R>::V *src,
+                                                                 typename CT<R>::V *dst,
+                                                                 const typename CT<R>::V *__restrict__ rows,
+                                                                 const typename CT<R>::V *__restrict__ rmul)
+{
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = threadIdx.x / kLanes;
+    const int64_t line = (int64_t)blockIdx.x * kRWaves + wave;
+    double nacc = 0.0;
+    if (line < P.nlines)  // uniform across the wavefront
+        radial_line_wave<R, MODE, FLAGS, Q>(P, src, dst, rows, rmul, line, lane, nacc);
     if (FLAGS & F_NORM_OUT) {
         __shared__ double red[kRWaves];
         nacc = wave_sum(nacc);
@@ -134,6 +146,56 @@ __global__ __launch_bounds__(kLanes *kRWaves) void k_radial_line(SweepParams P, 
             P.norm_out[blockIdx.x] = a;
         }
     }
+}
+
+// A circular or spherical run (one radial line) in one launch, as the
+// Cartesian 1D run: one wavefront takes the steps in turn through the line
+// kernel's routine and flags, with the imaginary-time norm total kept in LDS
+// (the separate launches sum the same value with zeros).  *total_out receives
+// the last step's total.
+template <int MODE, int Q>
+__global__ __launch_bounds__(kLanes) void k_radial_steps(SweepParams P, typename CT<double>::V *psi,
+                                                         const typename CT<double>::V *__restrict__ rows,
+                                                         const typename CT<double>::V *__restrict__ rmul,
+                                                         int64_t nsteps, double *total_out)
+{
+    constexpr bool kImag = MODE == GP_IMAG;
+    constexpr int kFlags = F_FUSE_N | (kImag ? F_NORM_OUT : 0);
+    const int lane = threadIdx.x & (kLanes - 1);
+    __shared__ double tot;
+    SweepParams Pr = P;  // renormalising steps read the previous step's total from LDS
+    Pr.norm_total = &tot;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        double nacc = 0.0;
+        if (kImag && k > 0)
+            radial_line_wave<double, MODE, kFlags | F_RENORM, Q>(Pr, psi, psi, rows, rmul, 0, lane, nacc);
+        else
+            radial_line_wave<double, MODE, kFlags, Q>(P, psi, psi, rows, rmul, 0, lane, nacc);
+        if constexpr (kImag) {
+            nacc = wave_sum(nacc);
+            __syncthreads();  // every lane has read the previous total
+            if (lane == 0) tot = nacc;
+            __syncthreads();
+        }
+    }
+    if (kImag && lane == 0 && nsteps > 0) *total_out = tot;
+}
+
+template <int MODE>
+hipError_t launch_radial_steps_mode(const SweepParams &P, const AxisPlan &A, void *psi, int64_t nsteps,
+                                    double *total_out, hipStream_t s)
+{
+    using V = CT<double>::V;
+    const V *rows = (const V *)A.d_rtab, *rmul = (const V *)A.d_rmul;
+    switch (A.rq) {
+    case 1: hipLaunchKernelGGL((k_radial_steps<MODE, 1>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, rows, rmul, nsteps, total_out); break;
+    case 2: hipLaunchKernelGGL((k_radial_steps<MODE, 2>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, rows, rmul, nsteps, total_out); break;
+    case 4: hipLaunchKernelGGL((k_radial_steps<MODE, 4>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, rows, rmul, nsteps, total_out); break;
+    case 8: hipLaunchKernelGGL((k_radial_steps<MODE, 8>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, rows, rmul, nsteps, total_out); break;
+    case 16: hipLaunchKernelGGL((k_radial_steps<MODE, 16>), dim3(1), dim3(kLanes), 0, s, P, (V *)psi, rows, rmul, nsteps, total_out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // Weighted norm partials sum w_i |psi_ij|^2 of an axial grid (rho fastest), one
@@ -263,6 +325,17 @@ hipError_t launch_radial_line(gp_plan *p, const void *src, void *dst, int flags,
     } else {
         e = flags == F_FUSE_N ? launch_line_flags<GP_REAL, F_FUSE_N>(P, p->ax[0], s) : hipErrorInvalidValue;
     }
+    timing_end(p, s);
+    return e;
+}
+
+hipError_t launch_radial_steps(gp_plan *p, void *psi, int64_t nsteps, double *total_out, hipStream_t s)
+{
+    const SweepParams P = make_sweep_params(p, 0, psi, psi, false, p->step, nullptr);
+    timing_begin(p, K_SWEEP_X, s);
+    const hipError_t e = p->mode == GP_IMAG
+                             ? launch_radial_steps_mode<GP_IMAG>(P, p->ax[0], psi, nsteps, total_out, s)
+                             : launch_radial_steps_mode<GP_REAL>(P, p->ax[0], psi, nsteps, total_out, s);
     timing_end(p, s);
     return e;
 }
