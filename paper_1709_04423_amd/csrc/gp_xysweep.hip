@@ -165,15 +165,16 @@ template <int N, typename F> __device__ __forceinline__ void static_for(F &&f)
 // S_m (the block's back substitution from a zero after it) is formed once when
 // block m is eliminated.  The output block then costs DW - 1 of those steps and
 // B - 1 single-point steps instead of (DW + 1) B - 1 of the latter -- the same
-// truncated window, summed in another order.  Used in complex128 imaginary time
-// only: in complex128 real time the DW + 1 sums would push the kernel past 256
-// registers (one wavefront per SIMD), and in complex64 the reordered sums bias
-// the long-run observables (after 2000 imaginary and 2000 real steps at 256^3
-// the chemical potential moves 4e-6 from the FP64 result instead of 3e-7).
-template <typename R, int MODE, int DW> struct YRegSolver {
+// truncated window, summed in another order.  SUMS selects it; the kernel uses
+// it in complex128 only -- in complex64 the reordered sums bias the long-run
+// observables (after 2000 imaginary and 2000 real steps at 256^3 the chemical
+// potential moves 4e-6 from the FP64 result instead of 3e-7) -- and in real
+// time only for rows of up to 128 points: with 4 points per lane the DW + 1
+// sums would push the kernel past 256 registers (one wavefront per SIMD).
+template <typename R, int MODE, int DW, bool SUMS> struct YRegSolver {
     using V = typename CT<R>::V;
     static constexpr int B = kXYWaves;
-    static constexpr bool kSums = sizeof(R) == 8 && MODE == GP_IMAG;
+    static constexpr bool kSums = SUMS;
     cp<R> d[DW + 1][B];
     cp<R> bs[kSums ? DW + 1 : 1];  // S_m of the block in each slot
     cp<R> um1, u0, dprev;
@@ -271,7 +272,8 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
     const int cw = (int)(nx / kLanes);
     const cp<R> zero = {R(0), R(0)};
 
-    YRegSolver<R, MODE, DW> Y;
+    constexpr bool kYSums = sizeof(R) == 8 && (MODE == GP_IMAG || Q <= 2);
+    YRegSolver<R, MODE, DW, kYSums> Y;
     {
         const int nb = PY.nblocks, segs = (int)gridDim.x, sg = (int)blockIdx.x;
         Y.o_lo = (int)((int64_t)sg * nb / segs);
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kLanes *kXYWaves) void k_sweep_xy_reg(SweepParams P
 #pragma unroll
             for (int r = 0; r < B; ++r) v[r] = from_v<R>(tile[j & 1][r][xy_slot<(int)sizeof(V)>(w * kLanes + lane)]);
             // one copy of the y step per window slot, so the slot index is a constant
-            const bool cr = YRegSolver<R, MODE, DW>::const_rows(j, PY.q_const, ny);
+            const bool cr = YRegSolver<R, MODE, DW, kYSums>::const_rows(j, PY.q_const, ny);
             static_for<DW + 1>([&](auto U) {
                 if (u == decltype(U)::value) {
                     if (cr)
